@@ -1,0 +1,154 @@
+"""Visibility texture and truncated-Gaussian approximation (FP64 test infrastructure).
+
+* Visibility (Section 3, last paragraph): a texel is marked visible when it
+  lies inside the cascade polygon.  Rays need all four corners of every cell
+  they may hit, so the reading here is: texture cell ``(i, j)`` spans texel
+  centres ``i..i+1, j..j+1``; a cell is active when its closed rectangle
+  meets the closed polygon (separating-axis test); a texel is visible when
+  any of its (up to four) incident cells is active.  Invisible texels hold
+  ``-inf``.
+* Eq. 1: ``w_j(p) = exp(-(|p_j - p| / c_j)^2 / (2 sigma^2)) - exp(-k^2 / 2)``
+  with the paper's ``k = 3.5``; here ``sigma`` may differ per leaf and ``k``
+  is a parameter.  Leaf ``j`` influences ``p`` iff ``w_j(p) > 0``.
+* Eq. 2: ``v(p) = sum_j w_j v_j / sum_j w_j`` over the influencing leaves.
+* A visible texel whose centre lies outside the domain is evaluated at the
+  centre clamped into the domain (reading; the paper is silent).
+
+Pinned by ``tests/test_oracle_discretize.py``: brute force over all leaves
+equals the range-query sum to 1e-12; a tilted plane on a uniform grid is
+reproduced exactly (symmetric neighbourhoods cancel first moments); the
+result stays within the influencing values; the truncated sum stays within
+the stated bound of the untruncated Gaussian sum; the mask against polygon
+clipping by rectangles.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+
+# ---------------------------------------------------------------- visibility
+
+def cell_active_sat(cas, i: np.ndarray, j: np.ndarray) -> np.ndarray:
+    """Separating-axis test of texture cells ``(i, j)`` against the closed cascade polygon."""
+    poly = np.asarray(cas.poly, np.float64)
+    i = np.asarray(i, np.float64)
+    j = np.asarray(j, np.float64)
+    if len(poly) == 0:
+        return np.zeros(i.shape, dtype=bool)
+    xa, xb = cas.x0 + i * cas.hx, cas.x0 + (i + 1.0) * cas.hx
+    ya, yb = cas.y0 + j * cas.hy, cas.y0 + (j + 1.0) * cas.hy
+    sep = (xb < poly[:, 0].min()) | (xa > poly[:, 0].max()) | (yb < poly[:, 1].min()) | (ya > poly[:, 1].max())
+    m = len(poly)
+    for a in range(m if m > 2 else m - 1):
+        p, q = poly[a], poly[(a + 1) % m]
+        nx, ny = -(q[1] - p[1]), q[0] - p[0]
+        proj_poly = poly[:, 0] * nx + poly[:, 1] * ny
+        lo_p, hi_p = proj_poly.min(), proj_poly.max()
+        c = np.stack([xa * nx + ya * ny, xb * nx + ya * ny, xa * nx + yb * ny, xb * nx + yb * ny])
+        sep |= (c.max(axis=0) < lo_p) | (c.min(axis=0) > hi_p)
+    return ~sep
+
+
+def visibility(cas) -> np.ndarray:
+    """Boolean ``[N][N]`` texel visibility (row = j)."""
+    N = cas.n
+    jj, ii = np.meshgrid(np.arange(N - 1), np.arange(N - 1), indexing="ij")
+    act = cell_active_sat(cas, ii, jj)
+    vis = np.zeros((N, N), dtype=bool)
+    vis[:-1, :-1] |= act
+    vis[:-1, 1:] |= act
+    vis[1:, :-1] |= act
+    vis[1:, 1:] |= act
+    return vis
+
+
+def texel_centres(cas, i: np.ndarray, j: np.ndarray) -> np.ndarray:
+    return np.stack([cas.x0 + np.asarray(i, np.float64) * cas.hx,
+                     cas.y0 + np.asarray(j, np.float64) * cas.hy], axis=-1)
+
+
+# ---------------------------------------------------------------- Eq. 1 / Eq. 2
+
+def weights(p: np.ndarray, xj, yj, cj, sj, cutoff: float) -> np.ndarray:
+    """Eq. 1 for points ``p (m, 2)`` against leaves ``j`` (broadcast ``(m, L)``), clipped at 0."""
+    r = np.hypot(np.asarray(xj, np.float64)[None, :] - p[:, 0:1], np.asarray(yj, np.float64)[None, :] - p[:, 1:2])
+    q = r / (np.asarray(sj, np.float64)[None, :] * np.asarray(cj, np.float64)[None, :])
+    w = np.exp(-0.5 * q * q) - math.exp(-0.5 * cutoff * cutoff)
+    return np.where(w > 0.0, w, 0.0)
+
+
+def clamp_to_domain(p: np.ndarray, dom) -> np.ndarray:
+    return np.stack([np.clip(p[:, 0], dom.x0, dom.x1), np.clip(p[:, 1], dom.y0, dom.y1)], axis=-1)
+
+
+def rbf_bruteforce(p: np.ndarray, leaves: dict, cutoff: float, chunk: int = 2048) -> tuple:
+    """Eq. 2 at points ``p`` summing over every leaf. Returns ``(value, sum_w)``."""
+    out_v = np.empty(len(p))
+    out_s = np.empty(len(p))
+    for a in range(0, len(p), chunk):
+        w = weights(p[a:a + chunk], leaves["x"], leaves["y"], leaves["c"], leaves["sigma"], cutoff)
+        s0 = w.sum(axis=1)
+        out_v[a:a + chunk] = (w @ np.asarray(leaves["v"], np.float64)) / s0
+        out_s[a:a + chunk] = s0
+    return out_v, out_s
+
+
+class RBFField:
+    """Eq. 2 by range queries: one k-d tree per cell size, radius = cutoff * max(sigma) * c."""
+
+    def __init__(self, leaves: dict, cutoff: float):
+        self.L = {k: np.asarray(leaves[k], np.float64) for k in ("x", "y", "c", "v", "sigma")}
+        self.cutoff = cutoff
+        self.groups = []
+        for c in np.unique(self.L["c"]):
+            idx = np.nonzero(self.L["c"] == c)[0]
+            tree = cKDTree(np.stack([self.L["x"][idx], self.L["y"][idx]], axis=1))
+            radius = cutoff * float(self.L["sigma"][idx].max()) * float(c)
+            self.groups.append((idx, tree, radius))
+
+    def candidates(self, p: np.ndarray) -> tuple:
+        """Flat ``(point_index, leaf_index)`` pairs of every leaf within its group radius."""
+        pi, lj = [], []
+        for idx, tree, radius in self.groups:
+            hits = tree.query_ball_point(p, radius)
+            lens = np.fromiter((len(h) for h in hits), dtype=np.int64, count=len(hits))
+            if lens.sum() == 0:
+                continue
+            pi.append(np.repeat(np.arange(len(p)), lens))
+            lj.append(idx[np.concatenate([np.asarray(h, np.int64) for h in hits if h])])
+        if not pi:
+            return np.zeros(0, np.int64), np.zeros(0, np.int64)
+        return np.concatenate(pi), np.concatenate(lj)
+
+    def evaluate(self, p: np.ndarray, return_terms: bool = False):
+        """``(value, sum_w)`` at points ``p``; optionally the flat ``(point, leaf, w)`` terms."""
+        pi, lj = self.candidates(p)
+        L = self.L
+        r = np.hypot(L["x"][lj] - p[pi, 0], L["y"][lj] - p[pi, 1])
+        q = r / (L["sigma"][lj] * L["c"][lj])
+        w = np.exp(-0.5 * q * q) - math.exp(-0.5 * self.cutoff * self.cutoff)
+        keep = w > 0.0
+        pi, lj, w = pi[keep], lj[keep], w[keep]
+        s0 = np.bincount(pi, weights=w, minlength=len(p))
+        s1 = np.bincount(pi, weights=w * L["v"][lj], minlength=len(p))
+        with np.errstate(invalid="ignore", divide="ignore"):
+            val = s1 / s0
+        return (val, s0, (pi, lj, w)) if return_terms else (val, s0)
+
+
+def discretize(cas, leaves: dict, dom, cutoff: float, field: RBFField = None) -> np.ndarray:
+    """FP64 cascade texture ``[N][N]``: Eq. 2 at visible texels, ``-inf`` elsewhere."""
+    N = cas.n
+    vis = visibility(cas)
+    tex = np.full((N, N), -np.inf)
+    jj, ii = np.nonzero(vis)
+    if len(jj) == 0:
+        return tex
+    p = clamp_to_domain(texel_centres(cas, ii, jj), dom)
+    if field is None:
+        field = RBFField(leaves, cutoff)
+    tex[jj, ii] = field.evaluate(p)[0]
+    return tex
