@@ -1,0 +1,270 @@
+/*
+ * hfr.h -- C ABI of the MI355X heightfield renderer library (libhfr.so).
+ *
+ * The library implements the per-frame path of the two-step adaptive
+ * heightfield renderer of Cornel, Horvath and Waser (2022): a truncated
+ * Gaussian approximation of an adaptive (quadtree) heightfield is
+ * discretized into view-dependent cascade textures, a maximum mipmap is
+ * built over each cascade, and every pixel is ray cast against the
+ * bilinear patches of the textures.  Gradients of the hit depth with
+ * respect to the leaf heights and Gaussian widths are provided as well.
+ *
+ * Conventions for every entry point:
+ *  - Arguments are validated on the host before anything is launched; an
+ *    invalid argument returns HFR_EINVAL and launches nothing.
+ *  - A non-zero status leaves a message for hfr_last_error() (per thread,
+ *    valid until the next call on that thread).  No C++ exception and no
+ *    abort crosses the ABI.
+ *  - "device" pointers are gfx950 device memory owned by the caller,
+ *    contiguous, naturally aligned.  "host" pointers are ordinary host
+ *    memory owned by the caller.  The library keeps no pointer after a
+ *    call returns; hfr_quadtree and hfr_neighbours objects own copies.
+ *  - Device work is enqueued on the given stream (a hipStream_t; NULL is
+ *    the null stream) and the call returns without synchronising; it
+ *    allocates no device memory, so it may be captured into a HIP graph.
+ *    Launch failures return HFR_EDEVICE.
+ *  - Coordinates: world x east, y north, z up, metres.  Textures are
+ *    row-major [k][j][i] with j the row (y) and i the column (x); texel
+ *    (i, j) of cascade k sits at (x0 + i hx, y0 + j hy).  Images are
+ *    row-major [row][col] with row 0 at the top.
+ */
+#ifndef HFR_H
+#define HFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HFR_ABI_VERSION 1
+#define HFR_MAX_POLY 32
+#define HFR_MAX_CASCADES 8
+#define HFR_MAX_TEX_N 8192
+
+typedef int32_t hfr_status;
+enum {
+    HFR_OK = 0,
+    HFR_EINVAL = -1,       /* invalid argument, nothing launched */
+    HFR_ENOMEM = -2,       /* host allocation failed */
+    HFR_EDEVICE = -3,      /* HIP runtime or launch error */
+    HFR_ECAPACITY = -4,    /* an output does not fit the space given */
+    HFR_EUNSUPPORTED = -5  /* valid but not supported by this build */
+};
+
+typedef void* hfr_stream; /* hipStream_t */
+
+/* Pinhole camera (the paper casts one ray per pixel, Section 5; the model
+ * itself is not stated there).  Forward is
+ * (sin yaw cos pitch, cos yaw cos pitch, sin pitch); yaw 0 looks along +y,
+ * pitch < 0 looks down; right = (cos yaw, -sin yaw, 0); up = right x forward.
+ * Pixel (col, row) is sampled at its centre, the image spans tan(vfov/2)
+ * vertically and tan(vfov/2) * width / height horizontally.  Rays have unit
+ * length, so depth is Euclidean distance.  znear bounds the frustum used
+ * for cascade fitting. */
+typedef struct {
+    double pos[3];
+    double yaw, pitch, vfov;
+    int32_t width, height;
+    double znear;
+} hfr_camera;
+
+/* Heightfield bounding box: the domain rectangle and the z-range of the
+ * leaf values (Eq. 2 is a convex combination, so the surface stays inside). */
+typedef struct {
+    double x0, y0, x1, y1, zmin, zmax;
+} hfr_domain;
+
+/* One cascade (Section 3).  The offset of a point p is
+ * d(p) = (p - origin) . vhat.  The cascade covers near_d <= d <= far_d;
+ * split_d is the split distance s_k, and the overlap with the next cascade
+ * is split_d <= d <= far_d (for the last cascade split_d == far_d).  The
+ * N x N texture maps texel (i, j) to (x0 + i hx, y0 + j hy); poly is the
+ * convex cascade polygon (counter-clockwise, n_poly vertices, possibly 0). */
+typedef struct {
+    double near_d, far_d, split_d;
+    double origin[2], vhat[2];
+    double x0, y0, hx, hy;
+    int32_t n, n_poly;
+    double poly[HFR_MAX_POLY][2];
+} hfr_cascade;
+
+/* Leaves of the adaptive grid on the device (all pointers device memory).
+ *  x, y, c, v, sigma : float[n]   centre, cell size, value, Gaussian width
+ *                                 (in units of the cell size)
+ *  packed            : float[4n]  (x, y, v, a) per leaf, written by
+ *                                 hfr_pack_leaves, read by hfr_discretize;
+ *                                 a = -log2(e) / (2 (sigma c)^2)
+ *  nbr_off, nbr_idx  : CSR influence lists (hfr_build_neighbours), n + 1
+ *                      offsets and nnz leaf indices
+ *  loc               : int32[loc_n * loc_n], the leaf containing each cell of
+ *                      the finest lattice (row-major, row = y), lattice origin
+ *                      (loc_x0, loc_y0) and cell size loc_cell
+ */
+typedef struct {
+    int64_t n;
+    const float* x;
+    const float* y;
+    const float* c;
+    const float* v;
+    const float* sigma;
+    float* packed;
+    const int32_t* nbr_off;
+    const int32_t* nbr_idx;
+    const int32_t* loc;
+    int32_t loc_n;
+    double loc_x0, loc_y0, loc_cell;
+} hfr_leaves;
+
+/* ------------------------------------------------------------------ misc */
+
+int hfr_abi_version(void);
+const char* hfr_last_error(void);
+/* HIP runtime version the library runs on (hipRuntimeGetVersion). */
+hfr_status hfr_runtime_version(int* version);
+
+/* ------------------------------------------------------------ start-up (host) */
+
+typedef struct hfr_quadtree hfr_quadtree;
+
+/* Adaptive quadtree over a square raster (the adaptive grid of Section 2;
+ * the paper takes it from a simulation and does not state a refinement
+ * rule).  dem: host float[n * n], row-major (row = y), n a power of two,
+ * samples at cell centres of a raster spanning [x0, x0 + side] x [y0, y0 + side].
+ * Level-l means are 2x2 averages ((a + b) + (c + d)) * 0.25 in FP64; a node
+ * at level l < max_depth splits when the largest |second difference| (x or
+ * y, edges replicated) of the level l + 1 means under it exceeds tau.  Leaves
+ * are listed depth-first with children (0,0), (1,0), (0,1), (1,1).
+ * Output: a library-owned object freed with hfr_quadtree_destroy.
+ * EINVAL: n not a power of two, max_depth outside [0, log2 n], side <= 0,
+ * non-finite samples.  Host only, synchronous. */
+hfr_status hfr_build_quadtree(const float* dem, int64_t n, double side, double x0, double y0,
+                              int32_t max_depth, double tau, hfr_quadtree** out);
+hfr_status hfr_quadtree_size(const hfr_quadtree* q, int64_t* n_leaves);
+/* Writes n_leaves entries to each non-NULL host array: centre (x, y), size c,
+ * mean value v (FP32), and the integer node (level, i, j). */
+hfr_status hfr_quadtree_export(const hfr_quadtree* q, float* x, float* y, float* c, float* v,
+                               int32_t* level, int32_t* i, int32_t* j);
+void hfr_quadtree_destroy(hfr_quadtree* q);
+
+/* Per-leaf lists of potentially influencing leaves (Section 4: the set I
+ * depends only on the grid and is precomputed at start-up).  Leaf j is in
+ * the list of leaf i iff dist(p_j, square_i)^2 < ((cutoff sigma_j) c_j (1 + slack))^2
+ * (FP64 on the FP32 inputs), so every j with w_j(p) > 0 for some p in
+ * square i is listed (Eq. 1).  Leaves must lie on the quadtree lattice of
+ * the square [x0, x0 + side] x [y0, y0 + side] with at most max_depth
+ * levels.  Host arrays x, y, c, sigma of n leaves.  Lists are sorted by
+ * leaf index.  Output: a library-owned object freed with
+ * hfr_neighbours_destroy.  EINVAL: off-lattice leaves, cutoff <= 0,
+ * slack < 0, more than INT32_MAX entries.  Host only, multi-threaded. */
+typedef struct hfr_neighbours hfr_neighbours;
+hfr_status hfr_build_neighbours(int64_t n, const float* x, const float* y, const float* c,
+                                const float* sigma, double x0, double y0, double side,
+                                int32_t max_depth, float cutoff, float slack, hfr_neighbours** out);
+hfr_status hfr_neighbours_size(const hfr_neighbours* nb, int64_t* nnz);
+/* Writes host off[n + 1] (CSR offsets) and idx[nnz] (leaf indices). */
+hfr_status hfr_neighbours_export(const hfr_neighbours* nb, int32_t* off, int32_t* idx);
+void hfr_neighbours_destroy(hfr_neighbours* nb);
+
+/* Point-location lattice: host loc[(2^max_depth)^2], the index of the leaf
+ * covering each finest-lattice cell (row-major, row = y).  Same lattice
+ * requirements as hfr_build_neighbours; EINVAL if the leaves do not tile
+ * the square exactly once. */
+hfr_status hfr_build_locator(int64_t n, const float* x, const float* y, const float* c, double x0,
+                             double y0, double side, int32_t max_depth, int32_t* loc);
+
+/* --------------------------------------------------------- per frame (host) */
+
+/* Cascade fitting (Section 3): frustum (near plane znear, no far plane)
+ * intersected with the domain box, projected to the ground plane, convex
+ * hull; n and f are the smallest and largest hull offsets along the
+ * horizontal view direction; splits
+ * s_k = lambda n' (f/n')^(k/K) + (1 - lambda) (n + (f - n) k / K) with
+ * n' = max(n, znear, c_min) (lambda = 1, K = 3 gives the paper's
+ * logarithmic splits); near_1 = n, near_{k+1} = s_k, far_k = s_k +
+ * overlap (s_k - near_k), far_K = f; each polygon is the hull clipped to
+ * [near_k, far_k]; its bounding box is widened to the c_min lattice and
+ * to an even multiple of c_min and mapped so its corners are the corner
+ * texel centres.  out: host hfr_cascade[K].
+ * EINVAL: K outside [1, HFR_MAX_CASCADES], N not a power of two in
+ * [2, HFR_MAX_TEX_N], horizontal view direction of zero length, non-finite
+ * input, c_min <= 0, lambda outside [0, 1], overlap < 0.  A frustum that
+ * misses the box yields cascades with n_poly == 0 (nothing visible). */
+hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N,
+                            double lambda, double overlap, double c_min, hfr_cascade* out);
+
+/* ------------------------------------------------------- per frame (device) */
+
+/* Writes L->packed from x, y, v, c, sigma.  EINVAL on NULL pointers or n < 1. */
+hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
+
+/* Discretization (Section 4, Eq. 1 and Eq. 2, and the visibility texture of
+ * Section 3).  For every texel of every cascade: the texel is visible when
+ * one of its (up to four) incident texture cells meets the closed cascade
+ * polygon; a visible texel holds
+ *   v_s = sum_j w_j v_j / sum_j w_j,
+ *   w_j = max(0, exp(-(|p_j - p_s| / (sigma_j c_j))^2 / 2) - exp(-cutoff^2 / 2)),
+ * evaluated at the texel centre clamped into the domain, summed over the
+ * influence list of the leaf containing that point; an invisible texel
+ * holds -inf.  tex: device float[K][N][N].  mask: device uint32
+ * [K][N][(N + 31) / 32] visibility bits (bit i % 32 of word i / 32), or NULL.
+ * A texel no leaf influences (impossible when cutoff sigma_j > sqrt(2)/2 for
+ * every leaf) holds NaN.  EINVAL: cascades with different N, N outside
+ * [2, HFR_MAX_TEX_N], cutoff <= 0, missing leaf arrays. */
+hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas,
+                          int32_t K, float cutoff, float* tex, uint32_t* mask, hfr_stream stream);
+
+/* Maximum mipmap (Tevs et al. 2008, used in Section 5).  Level 0 is N x N
+ * by texture cell: the largest of the cell's four corner texels, -inf when
+ * one is invisible, -inf on the last row and column; level l + 1 is the
+ * 2x2 maximum of level l, down to 1 x 1.  mip: device float[K][(4N^2-1)/3],
+ * levels finest first, each row-major.  EINVAL: N not a power of two in
+ * [2, HFR_MAX_TEX_N], K outside [1, HFR_MAX_CASCADES]. */
+hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, float* mip, hfr_stream stream);
+
+/* Ray casting (Section 5).  One ray per pixel, clipped to the domain's xy
+ * box and z <= zmax; the cascades are visited in the order the ray sweeps
+ * their offsets; inside a cascade the ray walks the maximum mipmap and
+ * stops at the first point at or below a bilinear patch of four visible
+ * texels.  When that first hit A lies in the overlap with the next cascade
+ * visited, that cascade is searched over the overlap only, and a hit B
+ * there gives depth (1 - a) t_nearer + a t_farther with
+ * a = clamp((d(t_A) - split) / (far - split), 0, 1) of the nearer cascade.
+ * depth: device float[H][W], +inf on a miss.  hit: device int32[H][W],
+ * (k << 26) | (j << 13) | i of hit A's cell, -1 on a miss.  Geometry is
+ * FP64 throughout.  EINVAL: image size outside [1, 16384], K/N as above. */
+hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                       int32_t K, const float* tex, const float* mip, float* depth, int32_t* hit,
+                       hfr_stream stream);
+
+/* Adjoint of hfr_raycast: recomputes every ray (nothing is stored by the
+ * forward pass) and ACCUMULATES into the caller-zeroed grad_tex
+ * (device float[K][N][N]) the derivative of sum(grad_depth * depth) with
+ * respect to the texel heights: dt/dh_c = phi_c(u, v) / f'(t) at a patch
+ * root (implicit function theorem on z(t) - B(u(t), v(t)) = 0), chained
+ * through the overlap blend; zero for hits at the start of a cascade
+ * segment.  grad_depth: device float[H][W] (ignored where the ray misses). */
+hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom,
+                                const hfr_cascade* cas, int32_t K, const float* tex,
+                                const float* mip, const float* grad_depth, float* grad_tex,
+                                hfr_stream stream);
+
+/* Adjoint of hfr_discretize (Eq. 2 and Eq. 1): ACCUMULATES into the
+ * caller-zeroed grad_v and grad_sigma (device float[n])
+ *   grad_v[j]     += g_s w_j / S0
+ *   grad_sigma[j] += g_s (v_j - v_s) / S0 * exp(-q^2/2) q^2 / sigma_j,
+ *   q = |p_j - p_s| / (sigma_j c_j),
+ * for every visible texel s with g_s = grad_tex[s] != 0, where S0 = sum_j w_j
+ * and v_s = tex[s] (the forward output).  Visibility and the cascade fit
+ * are treated as constants. */
+hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
+                                   const hfr_cascade* cas, int32_t K, float cutoff,
+                                   const float* tex, const float* grad_tex, float* grad_v,
+                                   float* grad_sigma, hfr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFR_H */

@@ -1,0 +1,249 @@
+"""Python binding of libhfr with the C ABI's names (argument marshalling only).
+
+Host entry points take and return NumPy arrays; device entry points take
+torch CUDA tensors (ROCm) and enqueue on torch's current stream unless a
+stream is given.  Every computation runs in libhfr; this module only checks
+shapes and dtypes and converts structures.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import Camera, Cascade, Domain, Leaves, call
+
+
+# ------------------------------------------------------------------ helpers
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def camera(cam) -> Camera:
+    c = Camera()
+    c.pos[:] = [float(v) for v in cam.pos]
+    c.yaw, c.pitch, c.vfov = float(cam.yaw), float(cam.pitch), float(cam.vfov)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(getattr(cam, "znear", 1.0))
+    return c
+
+
+def domain(dom) -> Domain:
+    return Domain(float(dom.x0), float(dom.y0), float(dom.x1), float(dom.y1), float(dom.zmin), float(dom.zmax))
+
+
+def cascades_from(objs: Sequence) -> ctypes.Array:
+    """Pack cascade descriptions (objects with near/far/split/origin/vhat/x0/y0/hx/hy/n/poly) for the ABI."""
+    arr = (Cascade * len(objs))()
+    for a, o in enumerate(objs):
+        c = arr[a]
+        c.near_d, c.far_d, c.split_d = float(o.near), float(o.far), float(o.split)
+        c.origin[:] = [float(o.origin[0]), float(o.origin[1])]
+        c.vhat[:] = [float(o.vhat[0]), float(o.vhat[1])]
+        c.x0, c.y0, c.hx, c.hy = float(o.x0), float(o.y0), float(o.hx), float(o.hy)
+        c.n = int(o.n)
+        poly = np.asarray(o.poly, np.float64).reshape(-1, 2)
+        if len(poly) > _lib.HFR_MAX_POLY:
+            raise ValueError("cascade polygon has too many vertices")
+        c.n_poly = len(poly)
+        for v in range(len(poly)):
+            c.poly[v][0], c.poly[v][1] = float(poly[v, 0]), float(poly[v, 1])
+    return arr
+
+
+class CascadeView:
+    """Read-only attribute view of one ABI cascade (same field names as the oracle's)."""
+
+    def __init__(self, c: Cascade):
+        self.near, self.far, self.split = c.near_d, c.far_d, c.split_d
+        self.origin = np.array(c.origin[:])
+        self.vhat = np.array(c.vhat[:])
+        self.x0, self.y0, self.hx, self.hy, self.n = c.x0, c.y0, c.hx, c.hy, c.n
+        self.poly = np.array([[c.poly[v][0], c.poly[v][1]] for v in range(c.n_poly)]).reshape(-1, 2)
+
+
+# ------------------------------------------------------------- start-up (host)
+
+def abi_version() -> int:
+    return _lib.load().hfr_abi_version()
+
+
+def runtime_version() -> int:
+    v = ctypes.c_int(0)
+    call("hfr_runtime_version", ctypes.byref(v))
+    return v.value
+
+
+def build_quadtree(dem: np.ndarray, side: float, max_depth: int, tau: float, x0: float = 0.0,
+                   y0: float = 0.0) -> dict:
+    dem = np.ascontiguousarray(dem, np.float32)
+    if dem.ndim != 2 or dem.shape[0] != dem.shape[1]:
+        raise ValueError("raster must be square")
+    q = ctypes.c_void_p()
+    call("hfr_build_quadtree", _np_ptr(dem), dem.shape[0], side, x0, y0, max_depth, tau, ctypes.byref(q))
+    lib = _lib.load()
+    try:
+        n = ctypes.c_int64()
+        call("hfr_quadtree_size", q, ctypes.byref(n))
+        out = {k: np.empty(n.value, np.float32) for k in ("x", "y", "c", "v")}
+        out.update({k: np.empty(n.value, np.int32) for k in ("level", "i", "j")})
+        call("hfr_quadtree_export", q, *(_np_ptr(out[k]) for k in ("x", "y", "c", "v", "level", "i", "j")))
+    finally:
+        lib.hfr_quadtree_destroy(q)
+    return out
+
+
+def build_neighbours(leaves: dict, side: float, max_depth: int, cutoff: float, slack: float = 1e-3,
+                     x0: float = 0.0, y0: float = 0.0) -> tuple:
+    arrs = [np.ascontiguousarray(leaves[k], np.float32) for k in ("x", "y", "c", "sigma")]
+    n = len(arrs[0])
+    h = ctypes.c_void_p()
+    call("hfr_build_neighbours", n, *(_np_ptr(a) for a in arrs), x0, y0, side, max_depth, cutoff, slack,
+         ctypes.byref(h))
+    lib = _lib.load()
+    try:
+        nnz = ctypes.c_int64()
+        call("hfr_neighbours_size", h, ctypes.byref(nnz))
+        off = np.empty(n + 1, np.int32)
+        idx = np.empty(max(nnz.value, 1), np.int32)[:nnz.value]
+        call("hfr_neighbours_export", h, _np_ptr(off), _np_ptr(idx))
+    finally:
+        lib.hfr_neighbours_destroy(h)
+    return off, idx
+
+
+def build_locator(leaves: dict, side: float, max_depth: int, x0: float = 0.0, y0: float = 0.0) -> np.ndarray:
+    arrs = [np.ascontiguousarray(leaves[k], np.float32) for k in ("x", "y", "c")]
+    S = 1 << max_depth
+    loc = np.empty((S, S), np.int32)
+    call("hfr_build_locator", len(arrs[0]), *(_np_ptr(a) for a in arrs), x0, y0, side, max_depth, _np_ptr(loc))
+    return loc
+
+
+def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: float) -> ctypes.Array:
+    out = (Cascade * K)()
+    call("hfr_fit_cascades", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), K, N, lam, overlap, c_min, out)
+    return out
+
+
+# ---------------------------------------------------------- per frame (device)
+
+class DeviceLeaves:
+    """Leaf arrays, influence lists and locator resident on the GPU (torch tensors)."""
+
+    def __init__(self, leaves: dict, off: np.ndarray, idx: np.ndarray, loc: np.ndarray, side: float,
+                 x0: float = 0.0, y0: float = 0.0, device: str = "cuda"):
+        import torch
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
+        i = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32), device=device)
+        self.x, self.y, self.c = f(leaves["x"]), f(leaves["y"]), f(leaves["c"])
+        self.v, self.sigma = f(leaves["v"]), f(leaves["sigma"])
+        self.off, self.idx = i(off), i(idx if len(idx) else np.zeros(1, np.int32))
+        self.loc = i(loc)
+        self.n = len(leaves["x"])
+        self.packed = torch.empty((self.n, 4), dtype=torch.float32, device=device)
+        self.loc_n = int(loc.shape[0])
+        self.loc_x0, self.loc_y0, self.loc_cell = float(x0), float(y0), float(side) / loc.shape[0]
+
+    def struct(self) -> Leaves:
+        import torch
+        for name in ("x", "y", "c", "v", "sigma", "packed"):
+            _dev(getattr(self, name), torch.float32, None, name)
+        return Leaves(self.n, self.x.data_ptr(), self.y.data_ptr(), self.c.data_ptr(), self.v.data_ptr(),
+                      self.sigma.data_ptr(), self.packed.data_ptr(), self.off.data_ptr(), self.idx.data_ptr(),
+                      self.loc.data_ptr(), self.loc_n, self.loc_x0, self.loc_y0, self.loc_cell)
+
+
+def pack_leaves(L: DeviceLeaves, stream=None) -> None:
+    call("hfr_pack_leaves", ctypes.byref(L.struct()), _stream(stream))
+
+
+def discretize(L: DeviceLeaves, dom, cascades: ctypes.Array, cutoff: float, tex=None, mask=None,
+               stream=None):
+    import torch
+    K, N = len(cascades), cascades[0].n
+    if tex is None:
+        tex = torch.empty((K, N, N), dtype=torch.float32, device=L.x.device)
+    tp = _dev(tex, torch.float32, (K, N, N), "tex")
+    mp = _dev(mask, torch.int32, (K, N, (N + 31) // 32), "mask") if mask is not None else None
+    call("hfr_discretize", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, cutoff, tp, mp,
+         _stream(stream))
+    return tex
+
+
+def mip_size(N: int) -> int:
+    return (4 * N * N - 1) // 3
+
+
+def build_maxmip(tex, mip=None, stream=None):
+    import torch
+    K, N = tex.shape[0], tex.shape[1]
+    if mip is None:
+        mip = torch.empty((K, mip_size(N)), dtype=torch.float32, device=tex.device)
+    call("hfr_build_maxmip", _dev(tex, torch.float32, (K, N, N), "tex"), K, N,
+         _dev(mip, torch.float32, (K, mip_size(N)), "mip"), _stream(stream))
+    return mip
+
+
+def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, stream=None):
+    import torch
+    K, N = len(cascades), cascades[0].n
+    if depth is None:
+        depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=tex.device)
+    if hit is None:
+        hit = torch.empty((cam.height, cam.width), dtype=torch.int32, device=tex.device)
+    call("hfr_raycast", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
+         _dev(depth, torch.float32, (cam.height, cam.width), "depth"),
+         _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _stream(stream))
+    return depth, hit
+
+
+def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, grad_tex=None, stream=None):
+    import torch
+    K, N = len(cascades), cascades[0].n
+    if grad_tex is None:
+        grad_tex = torch.zeros((K, N, N), dtype=torch.float32, device=tex.device)
+    call("hfr_raycast_backward", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
+         _dev(grad_depth, torch.float32, (cam.height, cam.width), "grad_depth"),
+         _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _stream(stream))
+    return grad_tex
+
+
+def discretize_backward(L: DeviceLeaves, dom, cascades: ctypes.Array, cutoff: float, tex, grad_tex,
+                        grad_v=None, grad_sigma=None, stream=None):
+    import torch
+    K, N = len(cascades), cascades[0].n
+    if grad_v is None:
+        grad_v = torch.zeros(L.n, dtype=torch.float32, device=tex.device)
+    if grad_sigma is None:
+        grad_sigma = torch.zeros(L.n, dtype=torch.float32, device=tex.device)
+    call("hfr_discretize_backward", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, cutoff,
+         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"),
+         _dev(grad_v, torch.float32, (L.n,), "grad_v"), _dev(grad_sigma, torch.float32, (L.n,), "grad_sigma"),
+         _stream(stream))
+    return grad_v, grad_sigma

@@ -1,0 +1,386 @@
+// Ray casting of the cascade textures (Section 5) and its adjoint.
+// gfx950, wave64.
+//
+// One thread per pixel; 16 x 16 pixel workgroups keep the rays of a wave
+// spatially coherent.  All geometry is FP64: gfx950 issues FP64 FMA at the
+// same rate as non-packed FP32, and FP64 makes the cell walk and the
+// patch root agree with an exact evaluation except on measure-zero ties.
+// Inside a cascade the ray descends the maximum mipmap: a node is skipped
+// when the ray's lowest z over its part of the node is above the node's
+// maximum; a level-0 cell whose four texels are visible is intersected
+// with the bilinear patch in closed form.  After a skip the walk climbs to
+// the highest level whose node the ray has newly entered.
+#include "hfr_device.h"
+
+namespace {
+
+struct RayCas {
+    double near_d, far_d, split_d, ox, oy, vx, vy, x0, y0, hx, hy, inv_hx, inv_hy;
+    int n, levels;
+};
+
+struct RayArgs {
+    double o[3], fwd[3], right[3], up[3];
+    double tx, ty;
+    int W, H, K, N;
+    double X0, Y0, X1, Y1, zmax;
+    RayCas c[HFR_MAX_CASCADES];
+};
+
+struct Ray {
+    double o[3], d[3], inv_d[2];
+};
+
+struct Hit {
+    int k, i, j, start;
+    double t, u, v, fp;
+};
+
+__device__ inline int64_t level_offset(int N, int l)
+{
+    const int64_t n = N, s = N >> l;
+    return (4 * n * n - 4 * s * s) / 3;
+}
+
+__device__ inline void slab(double o, double d, double lo, double hi, double& t0, double& t1)
+{
+    if (d == 0.0) {
+        if (o < lo || o > hi) {
+            t0 = INFINITY;
+            t1 = -INFINITY;
+        }
+        return;
+    }
+    const double a = (lo - o) / d, b = (hi - o) / d;
+    t0 = fmax(t0, fmin(a, b));
+    t1 = fmin(t1, fmax(a, b));
+}
+
+// t-range of the ray where lo <= d(t) <= hi and inside the texture rectangle,
+// intersected with [tin, tout].
+__device__ inline void segment(const Ray& r, const RayCas& c, double lo, double hi, double tin, double tout,
+                               double& ta, double& tb)
+{
+    ta = tin;
+    tb = tout;
+    const double d0 = (r.o[0] - c.ox) * c.vx + (r.o[1] - c.oy) * c.vy;
+    const double dd = r.d[0] * c.vx + r.d[1] * c.vy;
+    if (dd > 0.0) {
+        ta = fmax(ta, (lo - d0) / dd);
+        tb = fmin(tb, (hi - d0) / dd);
+    } else if (dd < 0.0) {
+        ta = fmax(ta, (hi - d0) / dd);
+        tb = fmin(tb, (lo - d0) / dd);
+    } else if (d0 < lo || d0 > hi) {
+        ta = INFINITY;
+        tb = -INFINITY;
+    }
+    slab(r.o[0], r.d[0], c.x0, lattice_pos(c.x0, c.n - 1, c.hx), ta, tb);
+    slab(r.o[1], r.d[1], c.y0, lattice_pos(c.y0, c.n - 1, c.hy), ta, tb);
+}
+
+__device__ inline double offset_at(const Ray& r, const RayCas& c, double t)
+{
+    return ((r.o[0] + t * r.d[0]) - c.ox) * c.vx + ((r.o[1] + t * r.d[1]) - c.oy) * c.vy;
+}
+
+// First t' > t at which one coordinate crosses a texel line base + m h.
+__device__ inline double next_crossing(double o, double d, double inv_d, double base, double h, double inv_h, double t)
+{
+    if (d == 0.0) return INFINITY;
+    const double w = ((o + t * d) - base) * inv_h;
+    double m = d > 0.0 ? floor(w) + 1.0 : ceil(w) - 1.0;
+    const double step = d > 0.0 ? 1.0 : -1.0;
+    for (int g = 0; g < 4; ++g) {
+        const double tm = (add_rn(base, mul_rn(m, h)) - o) * inv_d;
+        if (tm > t) return tm;
+        m += step;
+    }
+    return INFINITY;
+}
+
+__device__ inline double piece_end(const Ray& r, const RayCas& c, double t, double tb)
+{
+    return fmin(tb, fmin(next_crossing(r.o[0], r.d[0], r.inv_d[0], c.x0, c.hx, c.inv_hx, t),
+                         next_crossing(r.o[1], r.d[1], r.inv_d[1], c.y0, c.hy, c.inv_hy, t)));
+}
+
+__device__ inline void cell_at(const Ray& r, const RayCas& c, double t, int& i, int& j)
+{
+    i = (int)floor(((r.o[0] + t * r.d[0]) - c.x0) * c.inv_hx);
+    j = (int)floor(((r.o[1] + t * r.d[1]) - c.y0) * c.inv_hy);
+    i = min(max(i, 0), c.n - 2);
+    j = min(max(j, 0), c.n - 2);
+}
+
+// Smallest tau in [0, tau1] with a tau^2 + b tau + c <= 0, given c > 0.
+__device__ inline bool smallest_root(double a, double b, double c, double tau1, double& tau)
+{
+    double best = INFINITY;
+    if (a == 0.0) {
+        if (b < 0.0) {
+            const double q = -c / b;
+            if (q <= tau1) best = q;
+        }
+    } else {
+        const double D = b * b - 4.0 * a * c;
+        if (D >= 0.0) {
+            const double q = -0.5 * (b + copysign(sqrt(D), b));
+            const double r1 = q / a, r2 = c / q;
+            if (r1 >= 0.0 && r1 <= tau1) best = fmin(best, r1);
+            if (r2 >= 0.0 && r2 <= tau1) best = fmin(best, r2);
+        }
+    }
+    if (best == INFINITY) return false;
+    tau = best;
+    return true;
+}
+
+// Node of level l holding cell (ci, cj): exit parameter along the ray.
+__device__ inline double node_exit(const Ray& r, const RayCas& c, int ci, int cj, int l, double tb)
+{
+    double te = tb;
+    const int I = ci >> l, J = cj >> l;
+    if (r.d[0] > 0.0) te = fmin(te, (lattice_pos(c.x0, (I + 1) << l, c.hx) - r.o[0]) * r.inv_d[0]);
+    else if (r.d[0] < 0.0) te = fmin(te, (lattice_pos(c.x0, I << l, c.hx) - r.o[0]) * r.inv_d[0]);
+    if (r.d[1] > 0.0) te = fmin(te, (lattice_pos(c.y0, (J + 1) << l, c.hy) - r.o[1]) * r.inv_d[1]);
+    else if (r.d[1] < 0.0) te = fmin(te, (lattice_pos(c.y0, J << l, c.hy) - r.o[1]) * r.inv_d[1]);
+    return te;
+}
+
+__device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __restrict__ tex,
+                          const float* __restrict__ mip, double ta, double tb, Hit& h)
+{
+    if (!(ta < tb)) return false;
+    const int N = c.n, L = c.levels;
+    double t = ta;
+    double t1 = piece_end(r, c, t, tb);
+    int ci, cj;
+    cell_at(r, c, 0.5 * (t + t1), ci, cj);
+    int l = L;
+    // every iteration either descends a level or moves to a later piece
+    const int max_iter = 8 * N * (L + 2) + 64;
+    for (int it = 0; it < max_iter; ++it) {
+        const int S = N >> l;
+        const float M = mip[level_offset(N, l) + (int64_t)(cj >> l) * S + (ci >> l)];
+        const double te = fmax(node_exit(r, c, ci, cj, l, tb), t1);
+        const double za = r.o[2] + t * r.d[2], zb = r.o[2] + te * r.d[2];
+        bool advance = false;
+        if (fmin(za, zb) > (double)M) {
+            advance = true;
+        } else if (l > 0) {
+            --l;
+        } else {
+            const double h00 = tex[(int64_t)cj * N + ci], h10 = tex[(int64_t)cj * N + ci + 1];
+            const double h01 = tex[(int64_t)(cj + 1) * N + ci], h11 = tex[(int64_t)(cj + 1) * N + ci + 1];
+            const double u0 = ((r.o[0] + t * r.d[0]) - c.x0) * c.inv_hx - ci;
+            const double v0 = ((r.o[1] + t * r.d[1]) - c.y0) * c.inv_hy - cj;
+            const double du = r.d[0] * c.inv_hx, dv = r.d[1] * c.inv_hy;
+            const double A = h10 - h00, B = h01 - h00, C = (h00 - h10) - (h01 - h11);
+            const double cc = za - (h00 + A * u0 + B * v0 + C * u0 * v0);
+            const double bb = r.d[2] - A * du - B * dv - C * (u0 * dv + v0 * du);
+            const double aa = -C * du * dv;
+            double tau = 0.0;
+            if (cc <= 0.0 || smallest_root(aa, bb, cc, te - t, tau)) {
+                h.k = k;
+                h.i = ci;
+                h.j = cj;
+                h.t = t + tau;
+                h.u = u0 + tau * du;
+                h.v = v0 + tau * dv;
+                h.fp = 2.0 * aa * tau + bb;
+                h.start = (cc <= 0.0 && t == ta);
+                return true;
+            }
+            advance = true;
+        }
+        if (advance) {
+            if (te >= tb) return false;
+            t = te;
+            t1 = piece_end(r, c, t, tb);
+            int ni, nj;
+            cell_at(r, c, 0.5 * (t + t1), ni, nj);
+            const unsigned diff = (unsigned)((ni ^ ci) | (nj ^ cj));
+            ci = ni;
+            cj = nj;
+            if (diff) l = min(31 - __clz(diff), L);
+        }
+    }
+    return false;
+}
+
+template <bool BACKWARD>
+__global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
+                                                      const float* __restrict__ mip, float* __restrict__ depth,
+                                                      int32_t* __restrict__ hit, const float* __restrict__ gdepth,
+                                                      float* __restrict__ gtex)
+{
+    const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
+    if (col >= A.W || row >= A.H) return;
+    const int64_t p = (int64_t)row * A.W + col;
+    float g = 0.0f;
+    if (BACKWARD) {
+        g = gdepth[p];
+        if (g == 0.0f || !isfinite(g)) return;
+    }
+    const double sx = ((col + 0.5) / A.W) * 2.0 - 1.0;
+    const double sy = 1.0 - ((row + 0.5) / A.H) * 2.0;
+    Ray r;
+    double n2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = A.o[a];
+        r.d[a] = A.fwd[a] + (sx * A.tx) * A.right[a] + (sy * A.ty) * A.up[a];
+        n2 += r.d[a] * r.d[a];
+    }
+    const double inv_n = 1.0 / sqrt(n2);
+    for (int a = 0; a < 3; ++a) r.d[a] *= inv_n;
+    r.inv_d[0] = 1.0 / r.d[0];
+    r.inv_d[1] = 1.0 / r.d[1];
+
+    // clip to the domain box: xy slabs and z <= zmax
+    double tin = 0.0, tout = INFINITY;
+    slab(r.o[0], r.d[0], A.X0, A.X1, tin, tout);
+    slab(r.o[1], r.d[1], A.Y0, A.Y1, tin, tout);
+    if (r.d[2] > 0.0) tout = fmin(tout, (A.zmax - r.o[2]) / r.d[2]);
+    else if (r.d[2] < 0.0) tin = fmax(tin, (A.zmax - r.o[2]) / r.d[2]);
+    else if (r.o[2] > A.zmax) tin = INFINITY;
+
+    double out_t = INFINITY, cA = 0.0, cB = 0.0;
+    int hid = -1;
+    Hit HA, HB;
+    HB.k = -1;
+    bool found = false;
+    if (tin < tout) {
+        const double dd = r.d[0] * A.c[0].vx + r.d[1] * A.c[0].vy;
+        const bool fwd = dd >= 0.0;
+        for (int s = 0; s < A.K && !found; ++s) {
+            const int k = fwd ? s : A.K - 1 - s;
+            const RayCas& ck = A.c[k];
+            double ta, tb;
+            segment(r, ck, ck.near_d, ck.far_d, tin, tout, ta, tb);
+            const int64_t NN = (int64_t)A.N * A.N, MM = (4 * NN - 1) / 3;
+            if (!first_hit(r, ck, k, tex + k * NN, mip + k * MM, ta, tb, HA)) continue;
+            found = true;
+            hid = (HA.k << 26) | (HA.j << 13) | HA.i;
+            out_t = HA.t;
+            cA = 1.0;
+            const int pk = fwd ? k + 1 : k - 1;
+            if (pk >= 0 && pk < A.K) {
+                const RayCas& cov = A.c[fwd ? k : pk];
+                const double lo = cov.split_d, hi = cov.far_d;
+                const double dA = offset_at(r, ck, HA.t);
+                if (fwd ? dA >= lo : dA <= hi) {
+                    double tb0, tb1;
+                    segment(r, A.c[pk], lo, hi, tin, tout, tb0, tb1);
+                    if (first_hit(r, A.c[pk], pk, tex + pk * NN, mip + pk * MM, tb0, tb1, HB)) {
+                        const double delta = hi - lo;
+                        double al = (dA - lo) / delta, dal = dd / delta;
+                        if (al <= 0.0) { al = 0.0; dal = 0.0; }
+                        if (al >= 1.0) { al = 1.0; dal = 0.0; }
+                        if (fwd) {
+                            out_t = (1.0 - al) * HA.t + al * HB.t;
+                            cA = (1.0 - al) + (HB.t - HA.t) * dal;
+                            cB = al;
+                        } else {
+                            out_t = (1.0 - al) * HB.t + al * HA.t;
+                            cA = al + (HA.t - HB.t) * dal;
+                            cB = 1.0 - al;
+                        }
+                    } else {
+                        HB.k = -1;
+                    }
+                }
+            }
+        }
+    }
+    if (!BACKWARD) {
+        depth[p] = (float)out_t;
+        hit[p] = hid;
+        return;
+    }
+    if (!found) return;
+    const int N = A.N;
+    for (int x = 0; x < 2; ++x) {
+        const Hit& H = x ? HB : HA;
+        const double cf = x ? cB : cA;
+        if (H.k < 0 || H.start || !(H.fp < 0.0) || cf == 0.0) continue;
+        const double s = (double)g * cf / H.fp;
+        float* gk = gtex + (int64_t)H.k * N * N;
+        const double u = H.u, v = H.v;
+        atomicAdd(&gk[(int64_t)H.j * N + H.i], (float)(s * (1.0 - u) * (1.0 - v)));
+        atomicAdd(&gk[(int64_t)H.j * N + H.i + 1], (float)(s * u * (1.0 - v)));
+        atomicAdd(&gk[(int64_t)(H.j + 1) * N + H.i], (float)(s * (1.0 - u) * v));
+        atomicAdd(&gk[(int64_t)(H.j + 1) * N + H.i + 1], (float)(s * u * v));
+    }
+}
+
+hfr_status make_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K, RayArgs* A)
+{
+    HFR_REQUIRE(cam != nullptr, "camera is NULL");
+    hfr_status st = check_cascades(cas, K);
+    if (st == HFR_OK) st = check_domain(dom);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(cam->width >= 1 && cam->width <= 16384 && cam->height >= 1 && cam->height <= 16384,
+                "image size %dx%d outside [1, 16384]", cam->width, cam->height);
+    HFR_REQUIRE(std::isfinite(cam->pos[0]) && std::isfinite(cam->pos[1]) && std::isfinite(cam->pos[2]) &&
+                    std::isfinite(cam->yaw) && std::isfinite(cam->pitch) && cam->vfov > 0 && cam->vfov < M_PI,
+                "invalid camera");
+    const double cy = std::cos(cam->yaw), sy = std::sin(cam->yaw);
+    const double cp = std::cos(cam->pitch), sp = std::sin(cam->pitch);
+    const double f[3] = {sy * cp, cy * cp, sp}, rt[3] = {cy, -sy, 0.0};
+    const double up[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
+    for (int a = 0; a < 3; ++a) {
+        A->o[a] = cam->pos[a];
+        A->fwd[a] = f[a];
+        A->right[a] = rt[a];
+        A->up[a] = up[a];
+    }
+    A->ty = std::tan(0.5 * cam->vfov);
+    A->tx = A->ty * cam->width / cam->height;
+    A->W = cam->width;
+    A->H = cam->height;
+    A->K = K;
+    A->N = cas[0].n;
+    A->X0 = dom->x0;
+    A->Y0 = dom->y0;
+    A->X1 = dom->x1;
+    A->Y1 = dom->y1;
+    A->zmax = dom->zmax;
+    for (int k = 0; k < HFR_MAX_CASCADES; ++k) {
+        RayCas& c = A->c[k];
+        const hfr_cascade& s = cas[k < K ? k : 0];
+        c = RayCas{s.near_d, s.far_d, s.split_d, s.origin[0], s.origin[1], s.vhat[0], s.vhat[1],
+                   s.x0, s.y0, s.hx, s.hy, 1.0 / s.hx, 1.0 / s.hy, s.n, hfr_log2i(s.n)};
+    }
+    return HFR_OK;
+}
+
+}  // namespace
+
+extern "C" hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
+                                  const float* tex, const float* mip, float* depth, int32_t* hit, hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = make_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
+    const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
+    raycast_kernel<false><<<grid, dim3(16, 16), 0, (hipStream_t)stream>>>(A, tex, mip, depth, hit, nullptr, nullptr);
+    HFR_LAUNCH_CHECK("raycast");
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                                           int32_t K, const float* tex, const float* mip, const float* grad_depth,
+                                           float* grad_tex, hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = make_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && grad_depth && grad_tex, "NULL texture, mipmap or gradient");
+    const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
+    raycast_kernel<true><<<grid, dim3(16, 16), 0, (hipStream_t)stream>>>(A, tex, mip, nullptr, nullptr, grad_depth,
+                                                                         grad_tex);
+    HFR_LAUNCH_CHECK("raycast_backward");
+    return hfr_ok();
+}

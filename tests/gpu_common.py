@@ -1,0 +1,92 @@
+"""Shared pieces of the GPU parity tests: device inputs and comparison rules.
+
+Tolerances (the stated parity bar):
+* texel heights: |dv| <= 1e-5 * max(|v_oracle|, V), V = max |leaf value|;
+* hit depth: |dt| <= 1e-4 * scene extent;
+* hit cell: mismatches at most 1e-5 of the pixels, each one near-grazing
+  (ray within 2 degrees of the oracle patch's tangent plane) or with a
+  competing oracle root in the GPU's cell within 1e-4 * extent;
+* gradients: ||dg|| / ||g|| <= 1e-3 and per entry |dg| <= 1e-3 max(|g|, 1e-3 ||g||_inf).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import raycast as oray
+
+
+def device_leaves(scene, slack: float = 1e-3):
+    from paper_2201_10887_amd import api
+    w = scene.work
+    off, idx = api.build_neighbours(scene.leaves, w.side, w.max_depth, w.cutoff, slack)
+    loc = api.build_locator(scene.leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(scene.leaves, off, idx, loc, w.side)
+    api.pack_leaves(L)
+    return L
+
+
+def texel_tolerance(leaves, oracle_tex):
+    V = float(np.max(np.abs(leaves["v"])))
+    return 1e-5 * np.maximum(np.abs(oracle_tex), V)
+
+
+def grazing_deg(d, tex_k, cas, i, j, t, origin):
+    """Angle (degrees) between a ray and the tangent plane of patch (i, j) at the ray point t."""
+    p = np.asarray(origin) + t * np.asarray(d)
+    u = (p[0] - cas.x0) / cas.hx - i
+    v = (p[1] - cas.y0) / cas.hy - j
+    h00, h10 = tex_k[j, i], tex_k[j, i + 1]
+    h01, h11 = tex_k[j + 1, i], tex_k[j + 1, i + 1]
+    dBdx = ((h10 - h00) * (1 - v) + (h11 - h01) * v) / cas.hx
+    dBdy = ((h01 - h00) * (1 - u) + (h11 - h10) * u) / cas.hy
+    nrm = np.array([-dBdx, -dBdy, 1.0])
+    nrm /= np.linalg.norm(nrm)
+    return math.degrees(math.asin(min(1.0, abs(float(np.dot(nrm, d))))))
+
+
+def compare_hits(depth_gpu, hit_gpu, ref, cam, dom, cascades, tex, allow_rate=1e-5, what=""):
+    """Apply the hit-depth / hit-cell rules; returns (n_mismatch, n_pixels)."""
+    dg = np.asarray(depth_gpu, np.float64).ravel()
+    hg = np.asarray(hit_gpu).ravel()
+    do, ho = ref["depth"], ref["hit"]
+    ext = dom.extent
+    n = len(do)
+    assert dg.shape == do.shape
+    same_hit = hg == ho
+    both = np.isfinite(dg) & np.isfinite(do)
+    ok_depth = np.abs(dg - do) <= 1e-4 * ext
+    bad = np.nonzero(~same_hit | (both & ~ok_depth) | (np.isfinite(dg) != np.isfinite(do)))[0]
+    o = np.asarray(cam.pos, np.float64)
+    unexplained = []
+    for p in bad:
+        d = ref["dirs"][p]
+        explained = False
+        if hg[p] >= 0:
+            k, j, i = (int(v) for v in oray.unpack_hit(hg[p:p + 1]))
+            t_alt = oray.cell_root(o, d, cascades[k], tex[k], i, j)
+            t_ref = do[p] if np.isfinite(do[p]) else dg[p]
+            if t_alt is not None and abs(t_alt - t_ref) <= 1e-4 * ext and abs(dg[p] - t_alt) <= 1e-4 * ext:
+                explained = True
+        if not explained and ho[p] >= 0:
+            k, j, i = (int(v) for v in oray.unpack_hit(ho[p:p + 1]))
+            if grazing_deg(d, tex[k], cascades[k], i, j, do[p], o) < 2.0:
+                explained = True
+        if not explained:
+            unexplained.append(int(p))
+    msg = f"{what}: {len(bad)} mismatching pixels of {n}, unexplained {unexplained[:10]}"
+    assert not unexplained, msg
+    if allow_rate is not None:
+        assert len(bad) <= allow_rate * n, msg
+    return len(bad), n
+
+
+def grad_close(got, ref, rel=1e-3):
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    nrm = np.linalg.norm(ref)
+    assert nrm > 0
+    err = np.linalg.norm(got - ref) / nrm
+    per = np.abs(got - ref) <= rel * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    return err, per
