@@ -1,0 +1,107 @@
+"""Frame-level orchestration of the per-frame path on one GPU.
+
+``Renderer`` owns the device-resident heightfield (leaves, influence lists,
+point-location lattice) and the per-frame buffers (cascade textures,
+visibility bits, max-mipmaps), all allocated once; ``forward`` runs cascade
+fitting (host), discretize, max-mipmap and ray casting (device) on the
+current stream and allocates nothing.  ``RenderDepth`` is the
+``torch.autograd.Function`` that takes an image loss back to leaf values and
+Gaussian widths through the hand-written adjoints.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import api
+
+
+class Renderer:
+    def __init__(self, leaves: dict, side: float, max_depth: int, cutoff: float, cascades: int, tex_n: int,
+                 split_lambda: float, overlap: float, slack: float = 1e-3, device: str = "cuda",
+                 x0: float = 0.0, y0: float = 0.0):
+        import torch
+        self.side, self.max_depth, self.cutoff = float(side), int(max_depth), float(cutoff)
+        self.K, self.N, self.lam, self.overlap = int(cascades), int(tex_n), float(split_lambda), float(overlap)
+        self.c_min = float(np.min(leaves["c"]))
+        self.dom = api.domain(_Dom(x0, y0, x0 + side, y0 + side, float(np.min(leaves["v"])), float(np.max(leaves["v"]))))
+        off, idx = api.build_neighbours(leaves, side, max_depth, cutoff, slack, x0, y0)
+        loc = api.build_locator(leaves, side, max_depth, x0, y0)
+        self.nnz = int(len(idx))
+        self.L = api.DeviceLeaves(leaves, off, idx, loc, side, x0, y0, device=device)
+        api.pack_leaves(self.L)
+        K, N = self.K, self.N
+        self.tex = torch.empty((K, N, N), dtype=torch.float32, device=device)
+        self.mask = torch.empty((K, N, (N + 31) // 32), dtype=torch.int32, device=device)
+        self.mip = torch.empty((K, api.mip_size(N)), dtype=torch.float32, device=device)
+        self.device = device
+
+    @property
+    def domain(self):
+        return self.dom
+
+    def fit(self, cam):
+        return api.fit_cascades(cam, self.dom, self.K, self.N, self.lam, self.overlap, self.c_min)
+
+    def refresh_leaves(self, stream=None):
+        """Re-derive the packed leaf records after ``L.v`` or ``L.sigma`` changed."""
+        api.pack_leaves(self.L, stream)
+
+    def forward(self, cam, cascades=None, depth=None, hit=None, stream=None):
+        cas = self.fit(cam) if cascades is None else cascades
+        api.discretize(self.L, self.dom, cas, self.cutoff, self.tex, self.mask, stream)
+        api.build_maxmip(self.tex, self.mip, stream)
+        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream)
+        return depth, hit, cas
+
+    def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None):
+        """Accumulates into the (caller-zeroed) gradient buffers."""
+        api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream)
+        api.discretize_backward(self.L, self.dom, cascades, self.cutoff, self.tex, grad_tex, grad_v, grad_sigma,
+                                stream)
+        return grad_v, grad_sigma
+
+
+class _Dom:
+    def __init__(self, x0, y0, x1, y1, zmin, zmax):
+        self.x0, self.y0, self.x1, self.y1, self.zmin, self.zmax = x0, y0, x1, y1, zmin, zmax
+
+
+def _make_function():
+    import torch
+
+    class RenderDepth(torch.autograd.Function):
+        """depth = render(v, sigma); backward gives d loss / d v and d loss / d sigma."""
+
+        @staticmethod
+        def forward(ctx, v, sigma, renderer: Renderer, cam):
+            L = renderer.L
+            L.v.copy_(v.detach())
+            L.sigma.copy_(sigma.detach())
+            renderer.refresh_leaves()
+            depth, hit, cas = renderer.forward(cam)
+            ctx.renderer, ctx.cam, ctx.cas = renderer, cam, cas
+            ctx.mark_non_differentiable(hit)
+            return depth.clone(), hit.clone()
+
+        @staticmethod
+        def backward(ctx, grad_depth, grad_hit):
+            r = ctx.renderer
+            gd = torch.where(torch.isfinite(grad_depth), grad_depth, torch.zeros_like(grad_depth)).contiguous()
+            gtex = torch.zeros_like(r.tex)
+            gv = torch.zeros(r.L.n, dtype=torch.float32, device=r.tex.device)
+            gs = torch.zeros_like(gv)
+            r.backward(ctx.cam, ctx.cas, gd, gtex, gv, gs)
+            return gv, gs, None, None
+
+    return RenderDepth
+
+
+_RenderDepth = None
+
+
+def render_depth(v, sigma, renderer: Renderer, cam):
+    """Differentiable depth image (and non-differentiable hit ids) of leaf values ``v`` and widths ``sigma``."""
+    global _RenderDepth
+    if _RenderDepth is None:
+        _RenderDepth = _make_function()
+    return _RenderDepth.apply(v, sigma, renderer, cam)

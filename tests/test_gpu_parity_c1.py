@@ -90,8 +90,9 @@ def test_full_frame_matches_oracle(gpu, c1_scene, dev):
     mip = api.build_maxmip(tex)
     depth, hit = api.raycast(s.cam, s.dom, cas, tex, mip)
     ref = oray.raycast(s.cam, s.dom, s.cascades, s.tex64, threads=8)
+    V = float(np.abs(s.leaves["v"]).max())
     nbad, n = G.compare_hits(depth.cpu().numpy(), hit.cpu().numpy(), ref, s.cam, s.dom, s.cascades, s.tex64,
-                             allow_rate=None, what="C1 full frame")
+                             allow_rate=None, what="C1 full frame", height_tol=1e-5 * V)
     assert nbad <= 1e-3 * n
 
 
