@@ -50,43 +50,65 @@ def timed(fn, steps, stream):
     return a.elapsed_time(b) / steps
 
 
-def discretize_bytes(R, cas) -> tuple:
-    """Algorithmic bytes of one discretize pass and its (texel, listed leaf) pair count.
+def discretize_work(R, cas, leaves, w, samples=20000) -> dict:
+    """Algorithmic work of one discretize pass (all K launches), for the roofline.
 
-    Bytes: every texel's FP32 value and visibility bit written once; every
-    leaf containing a visible texel centre read once (its packed record,
-    its two list offsets and its list); every leaf on those lists read once
-    (packed record).  Computed with torch on the device as a measurement aid.
+    FLOPs: 12 per (visible texel, leaf with w > 0) pair -- two differences,
+    two products and a fused multiply-add for r^2, the exponent scale, one
+    exp2, the truncation subtraction and clamp, and a fused multiply-add plus
+    an add for the two sums.  The pair count is the visible-texel count times
+    the mean number of influencing leaves of a seeded sample of visible
+    texels (counted in FP64 from the library's host influence lists).
+    Bytes: every texel's FP32 value and visibility bit written once, and the
+    16-byte record of every leaf within reach of a cascade's polygon read once.
     """
     import torch
+    from paper_2201_10887_amd import api
     K, N = R.K, R.N
-    L = R.L
-    dev = R.tex.device
     words = (N + 31) // 32
-    bits = ((R.mask.view(torch.int32).unsqueeze(-1) >> torch.arange(32, device=dev, dtype=torch.int32)) & 1)
-    vis = bits.reshape(K, N, words * 32)[:, :, :N].bool()
-    owners, pairs = [], 0
+    m = R.mask.cpu().numpy().view(np.uint32)
+    vis = ((m[:, :, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(K, N, words * 32)[:, :, :N].astype(bool)
+    n_vis = int(vis.sum())
+    off, idx = api.build_neighbours(leaves, w.side, w.max_depth, w.cutoff)
+    x = leaves["x"].astype(np.float64)
+    y = leaves["y"].astype(np.float64)
+    c = leaves["c"].astype(np.float64)
+    sg = leaves["sigma"].astype(np.float64)
+    level = leaves["level"]
+    # containing leaf of a point: finest lattice cell, then walk up the node table
+    node = R.L.node.cpu().numpy()
+    rng = np.random.default_rng(11)
+    kk, jj, ii = np.nonzero(vis)
+    pick = rng.choice(len(kk), min(samples, len(kk)), replace=False)
+    counts = []
+    for a in pick:
+        cv = api.CascadeView(cas[kk[a]])
+        px = min(max(cv.x0 + ii[a] * cv.hx, 0.0), w.side)
+        py = min(max(cv.y0 + jj[a] * cv.hy, 0.0), w.side)
+        own = -1
+        for l in range(w.max_depth, -1, -1):
+            S = 1 << l
+            gi = min(int(px / (w.side / S)), S - 1)
+            gj = min(int(py / (w.side / S)), S - 1)
+            v = node[(4 ** l - 1) // 3 + gj * S + gi]
+            if v >= 0:
+                own = v
+                break
+        lst = idx[off[own]:off[own + 1]]
+        q = np.hypot(x[lst] - px, y[lst] - py) / (sg[lst] * c[lst])
+        counts.append(int(np.sum(np.exp(-0.5 * q * q) - np.exp(-0.5 * w.cutoff ** 2) > 0)))
+    pairs = n_vis * float(np.mean(counts))
+    nbytes = K * N * N * 4 + K * N * words * 4
     for k in range(K):
-        c = cas[k]
-        jj, ii = torch.nonzero(vis[k], as_tuple=True)
-        x = (c.x0 + ii.double() * c.hx).clamp(R.dom.x0, R.dom.x1)
-        y = (c.y0 + jj.double() * c.hy).clamp(R.dom.y0, R.dom.y1)
-        ix = ((x - L.loc_x0) / L.loc_cell).floor().long().clamp(0, L.loc_n - 1)
-        iy = ((y - L.loc_y0) / L.loc_cell).floor().long().clamp(0, L.loc_n - 1)
-        own = L.loc.view(-1)[iy * L.loc_n + ix].long()
-        lens = (L.off[own + 1] - L.off[own]).long()
-        pairs += int(lens.sum())
-        owners.append(own)
-    own = torch.unique(torch.cat(owners))
-    lens = (L.off[own + 1] - L.off[own]).long()
-    starts = L.off[own].long()
-    # union of the listed leaves
-    total = int(lens.sum())
-    seg = torch.repeat_interleave(torch.arange(len(own), device=dev), lens)
-    pos = torch.arange(total, device=dev) - torch.repeat_interleave(torch.cumsum(lens, 0) - lens, lens)
-    listed = torch.unique(L.idx[starts[seg] + pos].long())
-    nbytes = K * N * N * 4 + K * N * words * 4 + len(own) * (16 + 8) + total * 4 + len(listed) * 16
-    return nbytes, pairs, int(vis.sum())
+        cv = api.CascadeView(cas[k])
+        if len(cv.poly) == 0:
+            continue
+        reach = w.cutoff * sg * c
+        inside = ((x > cv.poly[:, 0].min() - reach) & (x < cv.poly[:, 0].max() + reach)
+                  & (y > cv.poly[:, 1].min() - reach) & (y < cv.poly[:, 1].max() + reach))
+        nbytes += 16 * int(inside.sum())
+    return {"flops": 12.0 * pairs, "bytes": float(nbytes), "pairs": pairs, "visible_texels": n_vis,
+            "mean_influencers": float(np.mean(counts))}
 
 
 def cpu_baseline(w, leaves, cam, R, cas, vis_texels, seconds=12.0):
@@ -162,7 +184,7 @@ def main():
     t0 = time.time()
     R = Renderer(leaves, w.side, w.max_depth, w.cutoff, w.cascades, w.tex_n, w.split_lambda, w.overlap)
     torch.cuda.synchronize()
-    print(f"[bench] renderer ready ({R.nnz} list entries) in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] renderer ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     H, W = cam.height, cam.width
     depth = torch.empty((H, W), dtype=torch.float32, device="cuda")
@@ -196,34 +218,39 @@ def main():
 
     # per-stage times on the same stream
     stage = {
-        "discretize": lambda: api.discretize(R.L, R.dom, cas, R.cutoff, R.tex, R.mask),
+        "discretize": lambda: api.discretize(R.L, R.dom, cas, R.tex, R.mask),
         "build_maxmip": lambda: api.build_maxmip(R.tex, R.mip),
         "raycast": lambda: api.raycast(cam, R.dom, cas, R.tex, R.mip, depth, hit),
         "raycast_backward": lambda: api.raycast_backward(cam, R.dom, cas, R.tex, R.mip, grad_depth, gtex),
-        "discretize_backward": lambda: api.discretize_backward(R.L, R.dom, cas, R.cutoff, R.tex, gtex, gv, gs),
+        "discretize_backward": lambda: api.discretize_backward(R.L, R.dom, cas, R.tex, gtex, gv, gs),
     }
     stage_ms = {k: timed(f, args.steps, stream) for k, f in stage.items()}
-    api.discretize(R.L, R.dom, cas, R.cutoff, R.tex, R.mask)
+    api.discretize(R.L, R.dom, cas, R.tex, R.mask)
     torch.cuda.synchronize()
     t_host = time.perf_counter()
     for _ in range(100):
         R.fit(cam)
     fit_us = (time.perf_counter() - t_host) * 1e4
 
-    nbytes, pairs, vis_texels = discretize_bytes(R, cas)
+    work = discretize_work(R, cas, leaves, w)
+    vis_texels, pairs = work["visible_texels"], work["pairs"]
     hits = int(torch.isfinite(depth).sum())
     K = R.K
-    disc_launch_ms = stage_ms["discretize"] / K
+    t_disc = stage_ms["discretize"] * 1e-3
+    t_alu_floor = work["flops"] / (FP32_PEAK_TFLOPS * 1e12)
+    t_hbm_floor = work["bytes"] / (HBM_PEAK_GBS * 1e9)
+    if t_alu_floor >= t_hbm_floor:
+        roof = {"bound": "alu", "achieved": round(work["flops"] / t_disc / 1e12, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(t_alu_floor / t_disc, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(work["bytes"] / t_disc / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(t_hbm_floor / t_disc, 4)}
+    roof.update({"traffic": None, "kernel": "discretize_kernel", "launches": K,
+                 "per_launch_ms": round(stage_ms["discretize"] / K, 4),
+                 "algorithmic_flops_per_launch": round(work["flops"] / K), "algorithmic_bytes_per_launch":
+                 round(work["bytes"] / K), "hbm_frac": round(t_hbm_floor / t_disc, 4),
+                 "alu_frac": round(t_alu_floor / t_disc, 4)})
     mip_bytes = K * (R.N * R.N * 4 + api.mip_size(R.N) * 4)
-    roof = {
-        "discretize": {"bound": "hbm", "achieved": round(nbytes / K / (disc_launch_ms * 1e-3) / 1e9, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(nbytes / (stage_ms["discretize"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                       "traffic": None, "kernel": "discretize_kernel", "per_launch_ms": round(disc_launch_ms, 4),
-                       "algorithmic_bytes_per_launch": int(nbytes / K),
-                       "alu_tflops": round(pairs * 12 / (stage_ms["discretize"] * 1e-3) / 1e12, 2),
-                       "alu_frac": round(pairs * 12 / (stage_ms["discretize"] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)},
-    }
     dominant = max(("discretize", "build_maxmip", "raycast"), key=lambda k: stage_ms[k])
     out = {
         "metric": "ms/frame at 1080p (Gtexel/s, Grays/s, %HBM roofline); fwd+bwd vs fwd time",
@@ -249,10 +276,11 @@ def main():
         "grays_per_s": round(W * H / (stage_ms["raycast"] * 1e-3) / 1e9, 3),
         "hit_fraction": round(hits / (W * H), 4),
         "visible_texels": vis_texels,
-        "pairs": pairs,
+        "pairs": round(pairs),
+        "mean_influencers": round(work["mean_influencers"], 2),
         "maxmip_hbm_frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "dominant_stage": dominant,
-        "roofline": roof["discretize"],
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         try:

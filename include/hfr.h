@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 1
+#define HFR_ABI_VERSION 2
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -90,17 +90,21 @@ typedef struct {
     double poly[HFR_MAX_POLY][2];
 } hfr_cascade;
 
-/* Leaves of the adaptive grid on the device (all pointers device memory).
+/* Leaves of the adaptive grid on the device (all pointers device memory,
+ * caller-owned).  The leaves lie on the quadtree lattice of the square
+ * [x0, x0 + side] x [y0, y0 + side], levels 0 .. max_depth.
  *  x, y, c, v, sigma : float[n]   centre, cell size, value, Gaussian width
  *                                 (in units of the cell size)
  *  packed            : float[4n]  (x, y, v, a) per leaf, written by
- *                                 hfr_pack_leaves, read by hfr_discretize;
- *                                 a = -log2(e) / (2 (sigma c)^2)
- *  nbr_off, nbr_idx  : CSR influence lists (hfr_build_neighbours), n + 1
- *                      offsets and nnz leaf indices
- *  loc               : int32[loc_n * loc_n], the leaf containing each cell of
- *                      the finest lattice (row-major, row = y), lattice origin
- *                      (loc_x0, loc_y0) and cell size loc_cell
+ *                                 hfr_pack_leaves; a = -log2(e) / (2 (sigma c)^2)
+ *  level_radius      : float[max_depth + 1], written by hfr_pack_leaves: the
+ *                      largest truncation radius cutoff * sigma_j * c_j of the
+ *                      leaves of each level (0 where a level has none)
+ *  node              : int32[(4^(max_depth+1) - 1) / 3], hfr_build_node_table:
+ *                      the leaf index of every lattice node, level by level
+ *                      (level l at offset (4^l - 1) / 3, row-major 2^l x 2^l,
+ *                      row = y), -1 for nodes that are not leaves
+ *  cutoff            : truncation radius in units of sigma (the paper's 3.5)
  */
 typedef struct {
     int64_t n;
@@ -110,11 +114,11 @@ typedef struct {
     const float* v;
     const float* sigma;
     float* packed;
-    const int32_t* nbr_off;
-    const int32_t* nbr_idx;
-    const int32_t* loc;
-    int32_t loc_n;
-    double loc_x0, loc_y0, loc_cell;
+    float* level_radius;
+    const int32_t* node;
+    int32_t max_depth;
+    float cutoff;
+    double x0, y0, side;
 } hfr_leaves;
 
 /* ------------------------------------------------------------------ misc */
@@ -167,12 +171,15 @@ hfr_status hfr_neighbours_size(const hfr_neighbours* nb, int64_t* nnz);
 hfr_status hfr_neighbours_export(const hfr_neighbours* nb, int32_t* off, int32_t* idx);
 void hfr_neighbours_destroy(hfr_neighbours* nb);
 
-/* Point-location lattice: host loc[(2^max_depth)^2], the index of the leaf
- * covering each finest-lattice cell (row-major, row = y).  Same lattice
- * requirements as hfr_build_neighbours; EINVAL if the leaves do not tile
- * the square exactly once. */
-hfr_status hfr_build_locator(int64_t n, const float* x, const float* y, const float* c, double x0,
-                             double y0, double side, int32_t max_depth, int32_t* loc);
+/* Dense lattice index of the leaves: host node[(4^(max_depth+1) - 1) / 3],
+ * the leaf index at every (level, i, j) node, -1 where the node is not a
+ * leaf (layout as in hfr_leaves.node).  Same lattice requirements as
+ * hfr_build_neighbours; EINVAL if the leaves do not tile the square exactly
+ * once or max_depth > 15.  It replaces per-cell influence buffers on the
+ * device: the influencers of any region are found by scanning, per level,
+ * the lattice window within that level's truncation radius. */
+hfr_status hfr_build_node_table(int64_t n, const float* x, const float* y, const float* c, double x0,
+                                double y0, double side, int32_t max_depth, int32_t* node);
 
 /* --------------------------------------------------------- per frame (host) */
 
@@ -196,7 +203,9 @@ hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_
 
 /* ------------------------------------------------------- per frame (device) */
 
-/* Writes L->packed from x, y, v, c, sigma.  EINVAL on NULL pointers or n < 1. */
+/* Writes L->packed and L->level_radius from x, y, v, c, sigma and cutoff
+ * (call again whenever v or sigma change).  EINVAL on NULL pointers,
+ * n < 1, cutoff <= 0, max_depth outside [0, 15]. */
 hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
 
 /* Discretization (Section 4, Eq. 1 and Eq. 2, and the visibility texture of
@@ -205,15 +214,15 @@ hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
  * polygon; a visible texel holds
  *   v_s = sum_j w_j v_j / sum_j w_j,
  *   w_j = max(0, exp(-(|p_j - p_s| / (sigma_j c_j))^2 / 2) - exp(-cutoff^2 / 2)),
- * evaluated at the texel centre clamped into the domain, summed over the
- * influence list of the leaf containing that point; an invisible texel
- * holds -inf.  tex: device float[K][N][N].  mask: device uint32
+ * evaluated at the texel centre clamped into the domain, summed over every
+ * leaf with w_j > 0 (found per tile of texels from L->node and
+ * L->level_radius); an invisible texel holds -inf.  tex: device float[K][N][N].  mask: device uint32
  * [K][N][(N + 31) / 32] visibility bits (bit i % 32 of word i / 32), or NULL.
  * A texel no leaf influences (impossible when cutoff sigma_j > sqrt(2)/2 for
  * every leaf) holds NaN.  EINVAL: cascades with different N, N outside
- * [2, HFR_MAX_TEX_N], cutoff <= 0, missing leaf arrays. */
+ * [2, HFR_MAX_TEX_N], missing leaf arrays. */
 hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas,
-                          int32_t K, float cutoff, float* tex, uint32_t* mask, hfr_stream stream);
+                          int32_t K, float* tex, uint32_t* mask, hfr_stream stream);
 
 /* Maximum mipmap (Tevs et al. 2008, used in Section 5).  Level 0 is N x N
  * by texture cell: the largest of the cell's four corner texels, -inf when
@@ -259,9 +268,9 @@ hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom,
  * and v_s = tex[s] (the forward output).  Visibility and the cascade fit
  * are treated as constants. */
 hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
-                                   const hfr_cascade* cas, int32_t K, float cutoff,
-                                   const float* tex, const float* grad_tex, float* grad_v,
-                                   float* grad_sigma, hfr_stream stream);
+                                   const hfr_cascade* cas, int32_t K, const float* tex,
+                                   const float* grad_tex, float* grad_v, float* grad_sigma,
+                                   hfr_stream stream);
 
 #ifdef __cplusplus
 }

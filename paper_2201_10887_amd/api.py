@@ -135,12 +135,15 @@ def build_neighbours(leaves: dict, side: float, max_depth: int, cutoff: float, s
     return off, idx
 
 
-def build_locator(leaves: dict, side: float, max_depth: int, x0: float = 0.0, y0: float = 0.0) -> np.ndarray:
+def node_table_size(max_depth: int) -> int:
+    return ((1 << (2 * (max_depth + 1))) - 1) // 3
+
+
+def build_node_table(leaves: dict, side: float, max_depth: int, x0: float = 0.0, y0: float = 0.0) -> np.ndarray:
     arrs = [np.ascontiguousarray(leaves[k], np.float32) for k in ("x", "y", "c")]
-    S = 1 << max_depth
-    loc = np.empty((S, S), np.int32)
-    call("hfr_build_locator", len(arrs[0]), *(_np_ptr(a) for a in arrs), x0, y0, side, max_depth, _np_ptr(loc))
-    return loc
+    node = np.empty(node_table_size(max_depth), np.int32)
+    call("hfr_build_node_table", len(arrs[0]), *(_np_ptr(a) for a in arrs), x0, y0, side, max_depth, _np_ptr(node))
+    return node
 
 
 def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: float) -> ctypes.Array:
@@ -152,44 +155,45 @@ def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: fl
 # ---------------------------------------------------------- per frame (device)
 
 class DeviceLeaves:
-    """Leaf arrays, influence lists and locator resident on the GPU (torch tensors)."""
+    """Leaf arrays, node table and per-level radii resident on the GPU (torch tensors)."""
 
-    def __init__(self, leaves: dict, off: np.ndarray, idx: np.ndarray, loc: np.ndarray, side: float,
+    def __init__(self, leaves: dict, node: np.ndarray, side: float, max_depth: int, cutoff: float,
                  x0: float = 0.0, y0: float = 0.0, device: str = "cuda"):
         import torch
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
-        i = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32), device=device)
         self.x, self.y, self.c = f(leaves["x"]), f(leaves["y"]), f(leaves["c"])
         self.v, self.sigma = f(leaves["v"]), f(leaves["sigma"])
-        self.off, self.idx = i(off), i(idx if len(idx) else np.zeros(1, np.int32))
-        self.loc = i(loc)
+        if len(node) != node_table_size(max_depth):
+            raise ValueError("node table size does not match max_depth")
+        self.node = torch.as_tensor(np.ascontiguousarray(node, np.int32), device=device)
         self.n = len(leaves["x"])
         self.packed = torch.empty((self.n, 4), dtype=torch.float32, device=device)
-        self.loc_n = int(loc.shape[0])
-        self.loc_x0, self.loc_y0, self.loc_cell = float(x0), float(y0), float(side) / loc.shape[0]
+        self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=device)
+        self.max_depth, self.cutoff = int(max_depth), float(cutoff)
+        self.x0, self.y0, self.side = float(x0), float(y0), float(side)
 
     def struct(self) -> Leaves:
         import torch
-        for name in ("x", "y", "c", "v", "sigma", "packed"):
+        for name in ("x", "y", "c", "v", "sigma", "packed", "level_radius"):
             _dev(getattr(self, name), torch.float32, None, name)
+        _dev(self.node, torch.int32, None, "node")
         return Leaves(self.n, self.x.data_ptr(), self.y.data_ptr(), self.c.data_ptr(), self.v.data_ptr(),
-                      self.sigma.data_ptr(), self.packed.data_ptr(), self.off.data_ptr(), self.idx.data_ptr(),
-                      self.loc.data_ptr(), self.loc_n, self.loc_x0, self.loc_y0, self.loc_cell)
+                      self.sigma.data_ptr(), self.packed.data_ptr(), self.level_radius.data_ptr(),
+                      self.node.data_ptr(), self.max_depth, self.cutoff, self.x0, self.y0, self.side)
 
 
 def pack_leaves(L: DeviceLeaves, stream=None) -> None:
     call("hfr_pack_leaves", ctypes.byref(L.struct()), _stream(stream))
 
 
-def discretize(L: DeviceLeaves, dom, cascades: ctypes.Array, cutoff: float, tex=None, mask=None,
-               stream=None):
+def discretize(L: DeviceLeaves, dom, cascades: ctypes.Array, tex=None, mask=None, stream=None):
     import torch
     K, N = len(cascades), cascades[0].n
     if tex is None:
         tex = torch.empty((K, N, N), dtype=torch.float32, device=L.x.device)
     tp = _dev(tex, torch.float32, (K, N, N), "tex")
     mp = _dev(mask, torch.int32, (K, N, (N + 31) // 32), "mask") if mask is not None else None
-    call("hfr_discretize", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, cutoff, tp, mp,
+    call("hfr_discretize", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, tp, mp,
          _stream(stream))
     return tex
 
@@ -234,15 +238,15 @@ def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, gra
     return grad_tex
 
 
-def discretize_backward(L: DeviceLeaves, dom, cascades: ctypes.Array, cutoff: float, tex, grad_tex,
-                        grad_v=None, grad_sigma=None, stream=None):
+def discretize_backward(L: DeviceLeaves, dom, cascades: ctypes.Array, tex, grad_tex, grad_v=None,
+                        grad_sigma=None, stream=None):
     import torch
     K, N = len(cascades), cascades[0].n
     if grad_v is None:
         grad_v = torch.zeros(L.n, dtype=torch.float32, device=tex.device)
     if grad_sigma is None:
         grad_sigma = torch.zeros(L.n, dtype=torch.float32, device=tex.device)
-    call("hfr_discretize_backward", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, cutoff,
+    call("hfr_discretize_backward", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K,
          _dev(tex, torch.float32, (K, N, N), "tex"), _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"),
          _dev(grad_v, torch.float32, (L.n,), "grad_v"), _dev(grad_sigma, torch.float32, (L.n,), "grad_sigma"),
          _stream(stream))

@@ -340,27 +340,41 @@ extern "C" hfr_status hfr_neighbours_export(const hfr_neighbours* nb, int32_t* o
 
 extern "C" void hfr_neighbours_destroy(hfr_neighbours* nb) { delete nb; }
 
-// ------------------------------------------------------------ point location
+// ------------------------------------------------------------ node table
 
-extern "C" hfr_status hfr_build_locator(int64_t n, const float* x, const float* y, const float* c, double x0,
-                                        double y0, double side, int32_t max_depth, int32_t* loc)
+extern "C" hfr_status hfr_build_node_table(int64_t n, const float* x, const float* y, const float* c, double x0,
+                                           double y0, double side, int32_t max_depth, int32_t* node)
 {
-    HFR_REQUIRE(loc != nullptr, "loc is NULL");
+    HFR_REQUIRE(node != nullptr, "node is NULL");
+    HFR_REQUIRE(max_depth >= 0 && max_depth <= 15, "max_depth %d outside [0, 15]", max_depth);
     LatticeLeaves lat;
     hfr_status st = lattice_of(n, x, y, c, x0, y0, side, max_depth, lat);
     if (st != HFR_OK) return st;
+    const int64_t total = ((int64_t(1) << (2 * (max_depth + 1))) - 1) / 3;
+    std::fill(node, node + total, -1);
+    // coverage count on the finest lattice detects gaps and overlaps
     const int64_t S = int64_t(1) << max_depth;
-    std::fill(loc, loc + S * S, -1);
+    std::vector<uint8_t> cover;
+    try {
+        cover.assign(S * S, 0);
+    } catch (const std::bad_alloc&) {
+        return hfr_fail(HFR_ENOMEM, "out of host memory");
+    }
     for (int64_t a = 0; a < n; ++a) {
-        const int sh = max_depth - lat.level[a];
+        const int l = lat.level[a];
+        const int64_t off = ((int64_t(1) << (2 * l)) - 1) / 3;
+        int32_t& slot = node[off + ((int64_t)lat.j[a] << l) + lat.i[a]];
+        HFR_REQUIRE(slot < 0, "leaves %d and %lld share a lattice node", slot, (long long)a);
+        slot = (int32_t)a;
+        const int sh = max_depth - l;
         const int64_t i0 = (int64_t)lat.i[a] << sh, j0 = (int64_t)lat.j[a] << sh, w = int64_t(1) << sh;
         for (int64_t jj = j0; jj < j0 + w; ++jj)
             for (int64_t ii = i0; ii < i0 + w; ++ii) {
-                HFR_REQUIRE(loc[jj * S + ii] < 0, "leaves %d and %lld overlap", loc[jj * S + ii], (long long)a);
-                loc[jj * S + ii] = (int32_t)a;
+                HFR_REQUIRE(cover[jj * S + ii] == 0, "leaf %lld overlaps another leaf", (long long)a);
+                cover[jj * S + ii] = 1;
             }
     }
-    for (int64_t a = 0; a < S * S; ++a) HFR_REQUIRE(loc[a] >= 0, "lattice cell %lld is not covered", (long long)a);
+    for (int64_t a = 0; a < S * S; ++a) HFR_REQUIRE(cover[a], "lattice cell %lld is not covered", (long long)a);
     return hfr_ok();
 }
 

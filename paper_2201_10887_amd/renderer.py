@@ -1,7 +1,7 @@
 """Frame-level orchestration of the per-frame path on one GPU.
 
-``Renderer`` owns the device-resident heightfield (leaves, influence lists,
-point-location lattice) and the per-frame buffers (cascade textures,
+``Renderer`` owns the device-resident heightfield (leaves, dense node
+table, per-level truncation radii) and the per-frame buffers (cascade textures,
 visibility bits, max-mipmaps), all allocated once; ``forward`` runs cascade
 fitting (host), discretize, max-mipmap and ray casting (device) on the
 current stream and allocates nothing.  ``RenderDepth`` is the
@@ -17,17 +17,15 @@ from . import api
 
 class Renderer:
     def __init__(self, leaves: dict, side: float, max_depth: int, cutoff: float, cascades: int, tex_n: int,
-                 split_lambda: float, overlap: float, slack: float = 1e-3, device: str = "cuda",
+                 split_lambda: float, overlap: float, device: str = "cuda",
                  x0: float = 0.0, y0: float = 0.0):
         import torch
         self.side, self.max_depth, self.cutoff = float(side), int(max_depth), float(cutoff)
         self.K, self.N, self.lam, self.overlap = int(cascades), int(tex_n), float(split_lambda), float(overlap)
         self.c_min = float(np.min(leaves["c"]))
         self.dom = api.domain(_Dom(x0, y0, x0 + side, y0 + side, float(np.min(leaves["v"])), float(np.max(leaves["v"]))))
-        off, idx = api.build_neighbours(leaves, side, max_depth, cutoff, slack, x0, y0)
-        loc = api.build_locator(leaves, side, max_depth, x0, y0)
-        self.nnz = int(len(idx))
-        self.L = api.DeviceLeaves(leaves, off, idx, loc, side, x0, y0, device=device)
+        node = api.build_node_table(leaves, side, max_depth, x0, y0)
+        self.L = api.DeviceLeaves(leaves, node, side, max_depth, cutoff, x0, y0, device=device)
         api.pack_leaves(self.L)
         K, N = self.K, self.N
         self.tex = torch.empty((K, N, N), dtype=torch.float32, device=device)
@@ -48,7 +46,7 @@ class Renderer:
 
     def forward(self, cam, cascades=None, depth=None, hit=None, stream=None):
         cas = self.fit(cam) if cascades is None else cascades
-        api.discretize(self.L, self.dom, cas, self.cutoff, self.tex, self.mask, stream)
+        api.discretize(self.L, self.dom, cas, self.tex, self.mask, stream)
         api.build_maxmip(self.tex, self.mip, stream)
         depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream)
         return depth, hit, cas
@@ -56,8 +54,7 @@ class Renderer:
     def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None):
         """Accumulates into the (caller-zeroed) gradient buffers."""
         api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream)
-        api.discretize_backward(self.L, self.dom, cascades, self.cutoff, self.tex, grad_tex, grad_v, grad_sigma,
-                                stream)
+        api.discretize_backward(self.L, self.dom, cascades, self.tex, grad_tex, grad_v, grad_sigma, stream)
         return grad_v, grad_sigma
 
 

@@ -17,12 +17,11 @@ import numpy as np
 from oracle import raycast as oray
 
 
-def device_leaves(scene, slack: float = 1e-3):
+def device_leaves(scene):
     from paper_2201_10887_amd import api
     w = scene.work
-    off, idx = api.build_neighbours(scene.leaves, w.side, w.max_depth, w.cutoff, slack)
-    loc = api.build_locator(scene.leaves, w.side, w.max_depth)
-    L = api.DeviceLeaves(scene.leaves, off, idx, loc, w.side)
+    node = api.build_node_table(scene.leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(scene.leaves, node, w.side, w.max_depth, w.cutoff)
     api.pack_leaves(L)
     return L
 

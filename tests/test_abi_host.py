@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 1
+    assert api.abi_version() == 2
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -68,19 +68,29 @@ def test_neighbours_and_locator_c1(c1_scene):
     off, idx = api.build_neighbours(L, w.side, w.max_depth, w.cutoff, 1e-3)
     ref = onb.influence_lists(L, w.cutoff, 1e-3)
     assert all(np.array_equal(idx[off[i]:off[i + 1]], ref[i]) for i in range(len(ref)))
-    loc = api.build_locator(L, w.side, w.max_depth)
-    S = 2 ** w.max_depth
-    cx = (np.arange(S) + 0.5) * w.side / S
-    px, py = np.meshgrid(cx, cx)
-    own = onb.containing_leaf(L, px.ravel(), py.ravel())
-    assert np.array_equal(loc.ravel(), own)
 
 
-def test_locator_rejects_gaps():
+@pytest.mark.parametrize("seed,depth,p", [(1, 5, 0.6), (2, 6, 0.45), (3, 0, 0.5)])
+def test_node_table(seed, depth, p):
+    struct = synth.random_leaf_structure(depth, p, seed)
+    n = len(struct)
+    L = synth.leaves_from_structure(struct, 640.0, np.zeros(n), np.ones(n))
+    node = api.build_node_table(L, 640.0, depth)
+    assert len(node) == (4 ** (depth + 1) - 1) // 3
+    want = np.full(len(node), -1, np.int64)
+    for a, (l, i, j) in enumerate(struct):
+        want[(4 ** l - 1) // 3 + j * 2 ** l + i] = a
+    assert np.array_equal(node, want)
+
+
+def test_node_table_rejects_gaps_and_overlaps():
     struct = synth.random_leaf_structure(3, 0.7, 5)
     L = synth.leaves_from_structure(struct[1:], 64.0, np.zeros(len(struct) - 1), np.ones(len(struct) - 1))
     with pytest.raises(_lib.HfrError, match="HFR_EINVAL"):
-        api.build_locator(L, 64.0, 3)
+        api.build_node_table(L, 64.0, 3)
+    L2 = synth.leaves_from_structure(struct + [(0, 0, 0)], 64.0, np.zeros(len(struct) + 1), np.ones(len(struct) + 1))
+    with pytest.raises(_lib.HfrError, match="HFR_EINVAL"):
+        api.build_node_table(L2, 64.0, 3)
 
 
 def _compare_cascades(a, b, scale):
@@ -165,11 +175,15 @@ def test_invalid_arguments_rejected_before_launch():
     # empty domain
     empty = api.domain(synth.Domain(0, 0, 0, 100, 0, 10))
     _raise_einval("hfr_raycast", ctypes.byref(cam), ctypes.byref(empty), cs, 2, dummy, dummy, dummy, dummy, None)
-    # discretize: missing lists, bad cutoff
-    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, None, None, None, 4, 0.0, 0.0, 1.0)
-    _raise_einval("hfr_discretize", ctypes.byref(L), ctypes.byref(dom), cs, 2, 3.5, dummy, None, None)
-    L2 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 0.0, 0.0, 1.0)
-    _raise_einval("hfr_discretize", ctypes.byref(L2), ctypes.byref(dom), cs, 2, -1.0, dummy, None, None)
+    # discretize: missing node table, bad cutoff, bad depth
+    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, 4, 3.5, 0.0, 0.0, 1.0)
+    _raise_einval("hfr_discretize", ctypes.byref(L), ctypes.byref(dom), cs, 2, dummy, None, None)
+    L2 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, -1.0, 0.0, 0.0, 1.0)
+    _raise_einval("hfr_discretize", ctypes.byref(L2), ctypes.byref(dom), cs, 2, dummy, None, None)
+    _raise_einval("hfr_pack_leaves", ctypes.byref(L2), None)
+    L3 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 16, 3.5, 0.0, 0.0, 1.0)
+    _raise_einval("hfr_discretize_backward", ctypes.byref(L3), ctypes.byref(dom), cs, 2, dummy, dummy, dummy,
+                  dummy, None)
     _raise_einval("hfr_pack_leaves", ctypes.byref(api.Leaves()), None)
     # fit: vertical view, N not a power of two, K out of range
     vert = api.camera(synth.Camera((50, 50, 50), 0.0, -math.pi / 2, 1.0, 64, 64))
@@ -182,4 +196,4 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 1
+    assert lib.hfr_abi_version() == 2

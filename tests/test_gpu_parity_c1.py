@@ -33,7 +33,7 @@ def test_discretize_matches_oracle(gpu, c1_scene, dev):
     L, cas = dev
     K, N = len(cas), cas[0].n
     mask = gpu.zeros((K, N, (N + 31) // 32), dtype=gpu.int32, device="cuda")
-    tex = api.discretize(L, s.dom, cas, s.work.cutoff, mask=mask).cpu().numpy()
+    tex = api.discretize(L, s.dom, cas, mask=mask).cpu().numpy()
     gpu.cuda.synchronize()
     ref = s.tex64
     vis_g, vis_o = np.isfinite(tex), np.isfinite(ref)
@@ -86,7 +86,7 @@ def test_full_frame_matches_oracle(gpu, c1_scene, dev):
     L, _ = dev
     w = s.work
     cas = api.fit_cascades(s.cam, s.dom, w.cascades, w.tex_n, w.split_lambda, w.overlap, float(s.leaves["c"].min()))
-    tex = api.discretize(L, s.dom, cas, w.cutoff)
+    tex = api.discretize(L, s.dom, cas)
     mip = api.build_maxmip(tex)
     depth, hit = api.raycast(s.cam, s.dom, cas, tex, mip)
     ref = oray.raycast(s.cam, s.dom, s.cascades, s.tex64, threads=8)
@@ -120,10 +120,10 @@ def test_discretize_backward_matches_oracle(gpu, c1_scene, dev):
     gd = rng.normal(0, 1, ref["depth"].shape) * np.isfinite(ref["depth"])
     gtex = adjoint.texel_gradients(ref, gd, len(cas), cas[0].n).astype(np.float32)
     gv_ref, gs_ref = adjoint.leaf_gradients(s.cascades, s.field, s.dom, gtex.astype(np.float64))
-    tex = api.discretize(L, s.dom, cas, s.work.cutoff)
+    tex = api.discretize(L, s.dom, cas)
     # the forward texel value enters the sigma gradient; give both sides the oracle's
     tex64 = gpu.as_tensor(s.tex32, device="cuda")
-    gv, gs = api.discretize_backward(L, s.dom, cas, s.work.cutoff, tex64, gpu.as_tensor(gtex, device="cuda"))
+    gv, gs = api.discretize_backward(L, s.dom, cas, tex64, gpu.as_tensor(gtex, device="cuda"))
     for got, want in ((gv, gv_ref), (gs, gs_ref)):
         err, per = G.grad_close(got.cpu().numpy(), want)
         assert err <= 1e-3, err
