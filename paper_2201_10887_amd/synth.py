@@ -126,13 +126,13 @@ class Workload:
 # counts (~2k for the tiny scene, ~4M for the medium one): with the
 # second-difference rule the stated 0.5 m and 0.2 m refine every node to the
 # maximum depth (4096 and 16.7M leaves).
-C1 = Workload(name="C1 tiny: 1 km fBm, depth 6, 2x256^2 cascades, 256x256",
+TINY = Workload(name="tiny: 1 km fBm, 2048 leaves (depth 6), 2x256^2 cascades, 256x256",
               side=1024.0, dem_n=256, octaves=8, hurst=0.8, seed=0, max_depth=6, tau=11.25,
               sigma=1.5, cutoff=3.0, cam_xy=(0.5, 0.05), cam_alt=100.0, yaw_deg=0.0,
               pitch_deg=-20.0, vfov_deg=60.0, width=256, height=256, cascades=2, tex_n=256,
               split_lambda=1.0)
 
-C2 = Workload(name="C2 medium: 40.96 km fBm, ~4M leaves, 4x2048^2 cascades, 1920x1080",
+MEDIUM = Workload(name="medium: 40.96 km fBm, 3.97M leaves (depth 12), 4x2048^2 cascades, 1920x1080",
               side=40960.0, dem_n=4096, octaves=12, hurst=0.8, seed=1, max_depth=12, tau=0.68,
               sigma=1.0, cutoff=3.5, cam_xy=(0.5, 0.05), cam_alt=200.0, yaw_deg=0.0,
               pitch_deg=-10.0, vfov_deg=60.0, width=1920, height=1080, cascades=4, tex_n=2048,
@@ -140,10 +140,10 @@ C2 = Workload(name="C2 medium: 40.96 km fBm, ~4M leaves, 4x2048^2 cascades, 1920
 
 # Paper-shaped context: the medium terrain with three 1024^2 cascades,
 # logarithmic splits, sigma 1 and a 3.5 sigma cutoff at 1080p (Section 6).
-P0 = dataclasses.replace(C2, name="P0 paper-shaped: C2 terrain, 3x1024^2 cascades, 1920x1080",
+PAPER = dataclasses.replace(MEDIUM, name="paper-shaped: medium terrain, 3x1024^2 cascades, 1920x1080",
                          cascades=3, tex_n=1024, split_lambda=1.0)
 
-WORKLOADS = {"C1": C1, "C2": C2, "P0": P0}
+WORKLOADS = {"tiny": TINY, "medium": MEDIUM, "paper": PAPER}
 
 
 def domain_of(w: Workload, dem: np.ndarray) -> Domain:

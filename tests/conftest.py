@@ -13,6 +13,6 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def c1_scene():
+def tiny_scene():
     from tests import scenes
-    return scenes.oracle_scene("C1")
+    return scenes.oracle_scene("tiny")

@@ -41,11 +41,11 @@ def test_quadtree_bitexact(n, depth, tau, seed):
         assert np.array_equal(a[k], b[k]), k
 
 
-def test_quadtree_c1_bitexact(c1_scene):
-    w = c1_scene.work
-    a = api.build_quadtree(c1_scene.dem, w.side, w.max_depth, w.tau)
+def test_quadtree_c1_bitexact(tiny_scene):
+    w = tiny_scene.work
+    a = api.build_quadtree(tiny_scene.dem, w.side, w.max_depth, w.tau)
     for k in ("x", "y", "c", "v", "level", "i", "j"):
-        assert np.array_equal(a[k], c1_scene.leaves[k]), k
+        assert np.array_equal(a[k], tiny_scene.leaves[k]), k
 
 
 @pytest.mark.parametrize("seed,depth,p,cutoff,sig", [(1, 5, 0.6, 3.5, None), (2, 6, 0.45, 3.0, 1.5),
@@ -63,8 +63,8 @@ def test_neighbours_equal_definition(seed, depth, p, cutoff, sig):
         assert np.array_equal(idx[off[i]:off[i + 1]], ref[i]), i
 
 
-def test_neighbours_and_locator_c1(c1_scene):
-    w, L = c1_scene.work, c1_scene.leaves
+def test_neighbours_and_locator_c1(tiny_scene):
+    w, L = tiny_scene.work, tiny_scene.leaves
     off, idx = api.build_neighbours(L, w.side, w.max_depth, w.cutoff, 1e-3)
     ref = onb.influence_lists(L, w.cutoff, 1e-3)
     assert all(np.array_equal(idx[off[i]:off[i + 1]], ref[i]) for i in range(len(ref)))
@@ -136,7 +136,7 @@ def test_fit_cascades_matches_oracle(pos, yaw, pitch, K, N, lam):
 
 def test_fit_cascades_c2_scene():
     dem = synth.fbm_dem(256, 8, 0.8, 1)
-    w = synth.C2
+    w = synth.MEDIUM
     dom = synth.Domain(0.0, 0.0, w.side, w.side, float(dem.min()), float(dem.max()))
     cam = synth.camera_of(w, dem * 0 + dem)
     got = [api.CascadeView(c) for c in api.fit_cascades(cam, dom, 4, 2048, 0.5, 0.05, 10.0)]

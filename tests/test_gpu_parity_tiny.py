@@ -22,14 +22,14 @@ def gpu():
 
 
 @pytest.fixture(scope="module")
-def dev(gpu, c1_scene):
-    L = G.device_leaves(c1_scene)
-    cas = api.cascades_from(c1_scene.cascades)
+def dev(gpu, tiny_scene):
+    L = G.device_leaves(tiny_scene)
+    cas = api.cascades_from(tiny_scene.cascades)
     return L, cas
 
 
-def test_discretize_matches_oracle(gpu, c1_scene, dev):
-    s = c1_scene
+def test_discretize_matches_oracle(gpu, tiny_scene, dev):
+    s = tiny_scene
     L, cas = dev
     K, N = len(cas), cas[0].n
     mask = gpu.zeros((K, N, (N + 31) // 32), dtype=gpu.int32, device="cuda")
@@ -50,11 +50,11 @@ def test_discretize_matches_oracle(gpu, c1_scene, dev):
     assert np.array_equal(bits, vis_o)
 
 
-def test_maxmip_bitexact(gpu, c1_scene):
-    tex = gpu.as_tensor(c1_scene.tex32, device="cuda")
+def test_maxmip_bitexact(gpu, tiny_scene):
+    tex = gpu.as_tensor(tiny_scene.tex32, device="cuda")
     mip = api.build_maxmip(tex).cpu().numpy()
     for k in range(tex.shape[0]):
-        ref = omip.flatten(omip.maxmip(c1_scene.tex32[k]))
+        ref = omip.flatten(omip.maxmip(tiny_scene.tex32[k]))
         assert np.array_equal(mip[k], ref.astype(np.float32))
 
 
@@ -68,21 +68,21 @@ def test_maxmip_small_sizes(gpu, N):
         assert np.array_equal(mip[k], omip.flatten(omip.maxmip(t[k])).astype(np.float32))
 
 
-def test_raycast_matches_oracle(gpu, c1_scene):
-    s = c1_scene
+def test_raycast_matches_oracle(gpu, tiny_scene):
+    s = tiny_scene
     cas = api.cascades_from(s.cascades)
     tex = gpu.as_tensor(s.tex32, device="cuda")
     mip = api.build_maxmip(tex)
     depth, hit = api.raycast(s.cam, s.dom, cas, tex, mip)
     ref = oray.raycast(s.cam, s.dom, s.cascades, s.tex32, threads=8)
     nbad, n = G.compare_hits(depth.cpu().numpy(), hit.cpu().numpy(), ref, s.cam, s.dom, s.cascades, s.tex32,
-                             what="C1 raycast")
+                             what="tiny raycast")
     assert np.isfinite(ref["depth"]).mean() > 0.5
 
 
-def test_full_frame_matches_oracle(gpu, c1_scene, dev):
+def test_full_frame_matches_oracle(gpu, tiny_scene, dev):
     """Each side runs its own cascade fit, discretization and ray cast."""
-    s = c1_scene
+    s = tiny_scene
     L, _ = dev
     w = s.work
     cas = api.fit_cascades(s.cam, s.dom, w.cascades, w.tex_n, w.split_lambda, w.overlap, float(s.leaves["c"].min()))
@@ -92,12 +92,12 @@ def test_full_frame_matches_oracle(gpu, c1_scene, dev):
     ref = oray.raycast(s.cam, s.dom, s.cascades, s.tex64, threads=8)
     V = float(np.abs(s.leaves["v"]).max())
     nbad, n = G.compare_hits(depth.cpu().numpy(), hit.cpu().numpy(), ref, s.cam, s.dom, s.cascades, s.tex64,
-                             allow_rate=None, what="C1 full frame", height_tol=1e-5 * V)
+                             allow_rate=None, what="tiny full frame", height_tol=1e-5 * V)
     assert nbad <= 1e-3 * n
 
 
-def test_raycast_backward_matches_oracle(gpu, c1_scene):
-    s = c1_scene
+def test_raycast_backward_matches_oracle(gpu, tiny_scene):
+    s = tiny_scene
     cas = api.cascades_from(s.cascades)
     tex = gpu.as_tensor(s.tex32, device="cuda")
     mip = api.build_maxmip(tex)
@@ -112,8 +112,8 @@ def test_raycast_backward_matches_oracle(gpu, c1_scene):
     assert per.mean() >= 0.999, per.mean()
 
 
-def test_discretize_backward_matches_oracle(gpu, c1_scene, dev):
-    s = c1_scene
+def test_discretize_backward_matches_oracle(gpu, tiny_scene, dev):
+    s = tiny_scene
     L, cas = dev
     ref = oray.raycast(s.cam, s.dom, s.cascades, s.tex32, threads=8)
     rng = np.random.default_rng(19)

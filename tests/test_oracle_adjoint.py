@@ -8,7 +8,7 @@ from tests import scenes
 
 
 def _small_scene(width=48, height=48, N=64):
-    s = scenes.oracle_scene("C1", with_tex=False)
+    s = scenes.oracle_scene("tiny", with_tex=False)
     cam = synth.Camera(s.cam.pos, s.cam.yaw, s.cam.pitch, s.cam.vfov, width, height)
     w = s.work
     cs = cascades.fit_cascades(cam, s.dom, w.cascades, N, w.split_lambda, w.overlap, float(s.leaves["c"].min()))

@@ -29,8 +29,8 @@ def test_range_query_equals_all_leaves(seed, depth, p, cutoff):
     assert np.allclose(a, b, rtol=0, atol=1e-12 * 300) and np.allclose(sa, sb, rtol=1e-12, atol=0)
 
 
-def test_range_query_equals_all_leaves_c1(c1_scene):
-    s = c1_scene
+def test_range_query_equals_all_leaves_c1(tiny_scene):
+    s = tiny_scene
     pts = np.random.default_rng(3).uniform(0, s.work.side, (3000, 2))
     a, _ = discretize.rbf_bruteforce(pts, s.leaves, s.work.cutoff)
     b, _ = s.field.evaluate(pts)
@@ -71,8 +71,8 @@ def test_plane_reproduced_on_uniform_grid(sigma, cutoff):
     assert np.abs(v - (a * pts[:, 0] + b * pts[:, 1] + c0)).max() < 1e-9
 
 
-def test_bounds_and_truncation(c1_scene):
-    s = c1_scene
+def test_bounds_and_truncation(tiny_scene):
+    s = tiny_scene
     L = {k: np.asarray(s.leaves[k], np.float64) for k in ("x", "y", "c", "v", "sigma")}
     k = s.work.cutoff
     pts = np.random.default_rng(11).uniform(0, s.work.side, (2000, 2))
@@ -135,8 +135,8 @@ def _rect_meets_convex(poly, xa, xb, ya, yb):
     return False
 
 
-def test_mask_against_bruteforce(c1_scene):
-    s = c1_scene
+def test_mask_against_bruteforce(tiny_scene):
+    s = tiny_scene
     rng = np.random.default_rng(5)
     for cas in s.cascades:
         N = cas.n
@@ -156,7 +156,7 @@ def test_mask_against_bruteforce(c1_scene):
         assert vis[:-1, :-1][act].all()
 
 
-def test_invisible_texels_are_minus_inf(c1_scene):
-    for cas, t in zip(c1_scene.cascades, c1_scene.tex64):
+def test_invisible_texels_are_minus_inf(tiny_scene):
+    for cas, t in zip(tiny_scene.cascades, tiny_scene.tex64):
         vis = discretize.visibility(cas)
         assert np.all(np.isneginf(t[~vis])) and np.all(np.isfinite(t[vis]))
