@@ -169,6 +169,8 @@ def main():
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device copy (known traffic) to calibrate hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each frame runs on one device)",
@@ -282,6 +284,13 @@ def main():
         "dominant_stage": dominant,
         "roofline": roof,
     }
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(w, leaves, cam, R, cas, vis_texels, args.cpu_seconds)

@@ -206,3 +206,11 @@ def leaves_from_structure(struct: List[Tuple[int, int, int]], side: float, value
     return dict(x=((ii + 0.5) * c).astype(np.float32), y=((jj + 0.5) * c).astype(np.float32),
                 c=c.astype(np.float32), v=np.asarray(values, np.float32),
                 sigma=np.asarray(sigma, np.float32), level=lv)
+
+
+def resample_raster(dem: np.ndarray, side: float, x0: float, y0: float, hx: float, hy: float, n: int) -> np.ndarray:
+    """Nearest raster sample at each point ``(x0 + i hx, y0 + j hy)``: a stand-in texture of a given shape."""
+    m = dem.shape[0]
+    gx = np.clip(np.floor((x0 + np.arange(n) * hx) / side * m).astype(np.int64), 0, m - 1)
+    gy = np.clip(np.floor((y0 + np.arange(n) * hy) / side * m).astype(np.int64), 0, m - 1)
+    return dem[np.ix_(gy, gx)].astype(np.float32)

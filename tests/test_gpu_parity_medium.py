@@ -1,0 +1,147 @@
+"""GPU parity at the medium scene's full size (3.97M leaves, 4 x 2048^2 cascades, 1920 x 1080).
+
+The GPU runs every kernel over the whole frame in the benchmark's launch
+configuration; the oracle recomputes seeded samples of the outputs one by one
+(texels, visibility over every cell, rays, gradients restricted to sampled
+pixels).  Both sides consume the oracle's leaves and cascades; the library's
+own quadtree and cascade fit are checked against them first.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint, cascades as ocas, discretize as odisc, maxmip as omip, quadtree as oqt, raycast as oray
+from paper_2201_10887_amd import api, synth
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def medium(gpu):
+    w = synth.MEDIUM
+    dem = synth.fbm_dem(w.dem_n, w.octaves, w.hurst, w.seed)
+    leaves = oqt.build_quadtree(dem, w.side, w.max_depth, w.tau)
+    leaves["sigma"] = np.full(len(leaves["x"]), w.sigma, np.float32)
+    dom = synth.Domain(0.0, 0.0, w.side, w.side, float(leaves["v"].min()), float(leaves["v"].max()))
+    cam = synth.camera_of(w, dem)
+    cs = ocas.fit_cascades(cam, dom, w.cascades, w.tex_n, w.split_lambda, w.overlap, float(leaves["c"].min()))
+    node = api.build_node_table(leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(leaves, node, w.side, w.max_depth, w.cutoff)
+    api.pack_leaves(L)
+    return dict(w=w, dem=dem, leaves=leaves, dom=dom, cam=cam, cs=cs, L=L, cas=api.cascades_from(cs))
+
+
+def test_library_quadtree_and_fit_match(medium):
+    w = medium["w"]
+    got = api.build_quadtree(medium["dem"], w.side, w.max_depth, w.tau)
+    for k in ("x", "y", "c", "v", "level", "i", "j"):
+        assert np.array_equal(got[k], medium["leaves"][k]), k
+    fit = api.fit_cascades(medium["cam"], medium["dom"], w.cascades, w.tex_n, w.split_lambda, w.overlap,
+                           float(medium["leaves"]["c"].min()))
+    for a, b in zip(fit, medium["cs"]):
+        for f_lib, f_ora in (("near_d", "near"), ("far_d", "far"), ("split_d", "split"), ("x0", "x0"),
+                             ("y0", "y0"), ("hx", "hx"), ("hy", "hy")):
+            assert abs(getattr(a, f_lib) - getattr(b, f_ora)) <= 1e-9 * medium["dom"].extent
+
+
+def test_discretize_full_frame_sampled(gpu, medium):
+    m = medium
+    K, N = len(m["cas"]), m["cas"][0].n
+    mask = gpu.zeros((K, N, (N + 31) // 32), dtype=gpu.int32, device="cuda")
+    tex = api.discretize(m["L"], m["dom"], m["cas"], mask=mask).cpu().numpy()
+    bits = mask.cpu().numpy().view(np.uint32)
+    vis_gpu = ((bits[:, :, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(K, N, -1)[:, :, :N].astype(bool)
+    assert np.array_equal(vis_gpu, np.isfinite(tex))
+    field = odisc.RBFField(m["leaves"], m["w"].cutoff)
+    rng = np.random.default_rng(2024)
+    for k, cas in enumerate(m["cs"]):
+        vis = odisc.visibility(cas)        # every texel of the cascade
+        assert np.array_equal(vis, vis_gpu[k]), f"cascade {k}: {np.argwhere(vis != vis_gpu[k])[:5]}"
+        jj, ii = np.nonzero(vis)
+        pick = rng.choice(len(jj), 4000, replace=False)
+        # plus all texels of a few random 8 x 8 tiles and the last row / column
+        extra = []
+        for _ in range(4):
+            a = pick[rng.integers(len(pick))]
+            tj, ti = (jj[a] // 8) * 8, (ii[a] // 8) * 8
+            extra += [(y, x) for y in range(tj, min(tj + 8, N)) for x in range(ti, min(ti + 8, N)) if vis[y, x]]
+        sj = np.concatenate([jj[pick], [e[0] for e in extra]]).astype(np.int64)
+        si = np.concatenate([ii[pick], [e[1] for e in extra]]).astype(np.int64)
+        p = odisc.clamp_to_domain(odisc.texel_centres(cas, si, sj), m["dom"])
+        ref, _ = field.evaluate(p)
+        got = tex[k][sj, si]
+        tol = G.texel_tolerance(m["leaves"], ref)
+        err = np.abs(got - ref)
+        assert np.all(err <= tol), f"cascade {k}: max error {err.max()} at {np.argmax(err - tol)}"
+
+
+@pytest.fixture(scope="module")
+def standin(gpu, medium):
+    """Stand-in textures of the full frame: the raster sampled at the texels, -inf where invisible."""
+    m = medium
+    tex = np.stack([synth.resample_raster(m["dem"], m["w"].side, c.x0, c.y0, c.hx, c.hy, c.n) for c in m["cs"]])
+    for k, c in enumerate(m["cs"]):
+        tex[k][~odisc.visibility(c)] = -np.inf
+    return tex
+
+
+def test_maxmip_full_size_bitexact(gpu, medium, standin):
+    mip = api.build_maxmip(gpu.as_tensor(standin, device="cuda")).cpu().numpy()
+    for k in range(len(standin)):
+        assert np.array_equal(mip[k], omip.flatten(omip.maxmip(standin[k])).astype(np.float32))
+
+
+def test_raycast_full_frame_sampled(gpu, medium, standin):
+    m = medium
+    tex = gpu.as_tensor(standin, device="cuda")
+    mip = api.build_maxmip(tex)
+    depth, hit = api.raycast(m["cam"], m["dom"], m["cas"], tex, mip)
+    depth, hit = depth.cpu().numpy().ravel(), hit.cpu().numpy().ravel()
+    cam = m["cam"]
+    rng = np.random.default_rng(7)
+    pix = rng.choice(cam.width * cam.height, 200_000, replace=False)
+    ref = oray.raycast(cam, m["dom"], m["cs"], standin, cols=pix % cam.width, rows=pix // cam.width, threads=16)
+    G.compare_hits(depth[pix], hit[pix], ref, cam, m["dom"], m["cs"], standin, what="medium raycast")
+    assert np.isfinite(ref["depth"]).mean() > 0.3
+
+
+def test_backward_full_frame_sampled(gpu, medium, standin):
+    m = medium
+    cam = m["cam"]
+    K, N = len(m["cas"]), m["cas"][0].n
+    tex = gpu.as_tensor(standin, device="cuda")
+    mip = api.build_maxmip(tex)
+    rng = np.random.default_rng(9)
+    pix = rng.choice(cam.width * cam.height, 50_000, replace=False)
+    ref = oray.raycast(cam, m["dom"], m["cs"], standin, cols=pix % cam.width, rows=pix // cam.width, threads=16)
+    g_pix = rng.normal(0, 1, len(pix)) * np.isfinite(ref["depth"])
+    gd = np.zeros(cam.width * cam.height, np.float32)
+    gd[pix] = g_pix
+    g_ref = adjoint.texel_gradients(ref, g_pix, K, N)
+    g_gpu = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip,
+                                 gpu.as_tensor(gd.reshape(cam.height, cam.width), device="cuda")).cpu().numpy()
+    err, per = G.grad_close(g_gpu, g_ref)
+    assert err <= 1e-3 and per.mean() >= 0.999, (err, per.mean())
+    # discretize adjoint on the same sparse texel gradient (the stand-in values enter the sigma term)
+    field = odisc.RBFField(m["leaves"], m["w"].cutoff)
+    gtex32 = g_ref.astype(np.float32)
+    gv_ref, gs_ref = adjoint.leaf_gradients(m["cs"], field, m["dom"], gtex32.astype(np.float64))
+    # the oracle's sigma term uses the oracle's texel values; feed the GPU those same values
+    tex_vals = np.full((K, N, N), -np.inf, np.float32)
+    for k, c in enumerate(m["cs"]):
+        jj, ii = np.nonzero(gtex32[k] != 0)
+        p = odisc.clamp_to_domain(odisc.texel_centres(c, ii, jj), m["dom"])
+        tex_vals[k][jj, ii] = field.evaluate(p)[0]
+    gv, gs = api.discretize_backward(m["L"], m["dom"], m["cas"], gpu.as_tensor(tex_vals, device="cuda"),
+                                     gpu.as_tensor(gtex32, device="cuda"))
+    for got, want in ((gv.cpu().numpy(), gv_ref), (gs.cpu().numpy(), gs_ref)):
+        err, per = G.grad_close(got, want)
+        assert err <= 1e-3 and per.mean() >= 0.999, (err, per.mean())
