@@ -95,8 +95,9 @@ typedef struct {
  * [x0, x0 + side] x [y0, y0 + side], levels 0 .. max_depth.
  *  x, y, c, v, sigma : float[n]   centre, cell size, value, Gaussian width
  *                                 (in units of the cell size)
- *  packed            : float[4n]  (x, y, v, a) per leaf, written by
- *                                 hfr_pack_leaves; a = -log2(e) / (2 (sigma c)^2)
+ *  packed            : float[4n]  (x, y, v, s) per leaf, written by
+ *                                 hfr_pack_leaves; s = sqrt(log2(e) / 2) / (sigma c),
+ *                                 so that Eq. 1's Gaussian is exp2(-(s r)^2)
  *  level_radius      : float[max_depth + 1], written by hfr_pack_leaves: the
  *                      largest truncation radius cutoff * sigma_j * c_j of the
  *                      leaves of each level (0 where a level has none)

@@ -2,21 +2,28 @@
 // textures (Eq. 1 and Eq. 2), with the visibility texture fused in, and its
 // adjoint.  gfx950, wave64.
 //
-// Work decomposition.  A workgroup covers a 32 x 8 texel block of one
-// cascade (one launch per cascade, so the cascade polygon travels as a
-// kernel argument); each of its four waves owns an 8 x 8 texel tile.
-//  1. The 9 cell rows touching the block get their polygon x-extent in LDS;
-//     every texel tests its incident cells; the visibility bits of the
-//     block's 8 rows (one 32-bit word each) are assembled with LDS atomics.
-//  2. A wave with a visible texel finds every leaf that can influence a
-//     point of its tile: per quadtree level, it scans the lattice window
-//     within that level's largest truncation radius of the tile rectangle
-//     in the dense node table (coalesced rows), keeps the leaves whose
-//     centre is closer than the radius to the rectangle (wave ballot +
-//     prefix count, no atomics), and stages their records in LDS in
-//     tile-local coordinates (FP64 subtraction, then FP32).
-//  3. Each lane (texel) runs Eq. 1 / Eq. 2 over the staged records with
-//     broadcast LDS reads: no divergent global load in the hot loop.
+// Work decomposition.  A workgroup (4 waves) covers a 16 x 16 texel block of
+// one cascade (one launch per cascade, so the cascade polygon travels as a
+// kernel argument); each wave owns one 8 x 8 tile of the block.
+//  1. Visibility: the 17 cell rows touching the block get their polygon
+//     x-extent in LDS; every texel tests its incident cells; the block's
+//     16-bit halves of the visibility words are assembled with LDS atomics.
+//  2. Block scan (all 256 lanes): per quadtree level, the lattice window
+//     within that level's largest truncation radius of the block rectangle
+//     is read from the dense node table (several independent loads in
+//     flight per lane); leaves whose centre is within the radius are
+//     appended in a fixed order (per-wave ballots and a 4-entry prefix).
+//  3. The block's leaf records are gathered once into LDS as (s x, s y, s, v),
+//     positions relative to the block origin (FP64 difference, then FP32),
+//     with s = sqrt(log2(e) / 2) / (sigma c) so that Eq. 1's Gaussian is
+//     exp2(-(s r)^2).
+//  4. Each wave keeps the records whose own truncation radius reaches its
+//     tile (a compact copy in LDS), and every lane (texel) runs Eq. 1 / Eq. 2
+//     over them with broadcast LDS reads and immediate offsets.  The inner
+//     loop sums max(g, E) and max(g, E) v; the constant E of the truncated
+//     Gaussian is subtracted once per tile list (E times the list length and
+//     E times the sum of its values), which is the same sum as
+//     sum max(g - E, 0) and sum max(g - E, 0) v.
 // More candidates than fit in LDS are handled in rounds (rescan, next slice).
 #include <cmath>
 
@@ -24,9 +31,12 @@
 
 namespace {
 
-constexpr int TS = 8;        // tile side in texels (one wave)
-constexpr int WAVES = 4;     // tiles per workgroup, side by side along x
-constexpr int CAP = 512;     // candidate records staged per round
+constexpr int BS = 16;        // block side in texels
+constexpr int TS = 8;         // tile side in texels (one wave)
+constexpr int WAVES = 4;      // 2 x 2 tiles per block
+constexpr int BCAP = 512;     // block candidates staged per round
+constexpr int TCAP = 128;     // tile-list records per chunk
+constexpr int UNROLL = 2;     // node-table loads in flight per lane during the scan
 constexpr float LOG2E = 1.4426950408889634f;
 
 struct Tables {
@@ -35,11 +45,18 @@ struct Tables {
     const int32_t* node;
     const float* sigma;
     int n, max_depth;
-    double x0, y0, side;
-    float E;  // exp(-cutoff^2 / 2)
+    double x0, y0, side, inv_side;
+    float E;   // exp(-cutoff^2 / 2)
+    float T2;  // (s r)^2 at the truncation radius: cutoff^2 log2(e) / 2
 };
 
+constexpr float HALF_LOG2E = 0.72134752044448170f;
+
 struct Dom2 {
+    double x0, y0, x1, y1;
+};
+
+struct Rect {
     double x0, y0, x1, y1;
 };
 
@@ -52,7 +69,7 @@ __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restric
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
     const float sc = sigma[a] * c[a];
-    out[a] = make_float4(x[a], y[a], v[a], -0.5f * LOG2E / (sc * sc));
+    out[a] = make_float4(x[a], y[a], v[a], sqrtf(HALF_LOG2E) / sc);
     int l = (int)rintf(log2f(side / c[a]));
     l = min(max(l, 0), max_depth);
     const float R = cutoff * sc * 1.00001f;
@@ -65,41 +82,35 @@ __global__ void zero_floats_kernel(float* __restrict__ p, int n)
     if (a < n) p[a] = 0.0f;
 }
 
-__device__ inline bool texel_visible(const TexCascade& C, const double* rxl, const double* rxr, int j0, int i, int j)
-{
-    const int N = C.n;
-    bool vis = false;
-    for (int dj = -1; dj <= 0; ++dj) {
-        const int jc = j + dj;
-        if (jc < 0 || jc > N - 2) continue;
-        const double xl = rxl[jc - (j0 - 1)], xr = rxr[jc - (j0 - 1)];
-        for (int di = -1; di <= 0; ++di) {
-            const int ic = i + di;
-            if (ic < 0 || ic > N - 2) continue;
-            const double xa = lattice_pos(C.x0, ic, C.hx), xb = lattice_pos(C.x0, ic + 1, C.hx);
-            vis |= (xa <= xr) && (xb >= xl);
-        }
-    }
-    return vis;
-}
-
 __device__ inline double clampd(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
 
-// Tile rectangle (clamped texel centres) of the wave's 8 x 8 tile.
-struct TileRect {
-    double x0, y0, x1, y1;
-};
-
-__device__ inline TileRect tile_rect(const TexCascade& C, const Dom2& D, int ti0, int tj0)
+// Clamped centres of texels [i0, i0 + w) x [j0, j0 + h) (cut at N - 1).
+__device__ inline Rect texel_rect(const TexCascade& C, const Dom2& D, int i0, int j0, int w, int h)
 {
     const int N = C.n;
-    const int ti1 = min(ti0 + TS - 1, N - 1), tj1 = min(tj0 + TS - 1, N - 1);
-    TileRect r;
-    r.x0 = clampd(lattice_pos(C.x0, ti0, C.hx), D.x0, D.x1);
-    r.x1 = clampd(lattice_pos(C.x0, ti1, C.hx), D.x0, D.x1);
-    r.y0 = clampd(lattice_pos(C.y0, tj0, C.hy), D.y0, D.y1);
-    r.y1 = clampd(lattice_pos(C.y0, tj1, C.hy), D.y0, D.y1);
+    const int i1 = min(i0 + w - 1, N - 1), j1 = min(j0 + h - 1, N - 1);
+    Rect r;
+    r.x0 = clampd(lattice_pos(C.x0, min(i0, N - 1), C.hx), D.x0, D.x1);
+    r.x1 = clampd(lattice_pos(C.x0, i1, C.hx), D.x0, D.x1);
+    r.y0 = clampd(lattice_pos(C.y0, min(j0, N - 1), C.hy), D.y0, D.y1);
+    r.y1 = clampd(lattice_pos(C.y0, j1, C.hy), D.y0, D.y1);
     return r;
+}
+
+// Block (bx, by) of this workgroup.  The hardware deals consecutive
+// workgroups round-robin to the 8 XCDs; remapping gives each XCD one
+// contiguous run of blocks, so neighbouring blocks (which read the same
+// node-table rows and leaf records) share an L2.
+__device__ inline void block_coords(int gx, int gy, int* bx, int* by)
+{
+    const int nb = gx * gy;
+    const int b = blockIdx.x;
+    const int per = (nb + 7) / 8;
+    const int xcd = b & 7, slot = b >> 3;
+    const int full = nb - 8 * (per - 1);  // XCDs that receive `per` blocks (the rest get per - 1)
+    const int lin = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
+    *bx = lin % gx;
+    *by = lin / gx;
 }
 
 __device__ inline void wave_sync()
@@ -108,11 +119,56 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Appends to rec (and ids) the candidates with rank in [lo, lo + CAP) of the
-// deterministic scan order (level, row, column); returns the total count.
-template <bool WITH_IDS>
-__device__ int scan_candidates(const Tables& T, const TileRect& r, int lo, float4* rec, int* ids, float* sig,
-                               int lane)
+__device__ inline float wave_sum(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Visibility of the block's texels; returns this lane's texel visibility and
+// writes the block's 16-bit visibility half-words.  Block-uniform helpers
+// live in LDS: rxl / rxr (17 cell-row extents), mbits (16 rows).
+__device__ inline bool block_visibility(const TexCascade& C, int bi0, int bj0, int i, int j, double* rxl, double* rxr,
+                                        uint32_t* mbits, uint16_t* mask)
+{
+    const int N = C.n;
+    const int t = threadIdx.x;
+    if (t <= BS) {
+        const int jc = bj0 - 1 + t;
+        double lo = INFINITY, hi = -INFINITY;
+        if (jc >= 0 && jc <= N - 2) strip_extent(C, lattice_pos(C.y0, jc, C.hy), lattice_pos(C.y0, jc + 1, C.hy), &lo, &hi);
+        rxl[t] = lo;
+        rxr[t] = hi;
+    }
+    if (t < BS) mbits[t] = 0u;
+    __syncthreads();
+    bool vis = false;
+    if (i < N && j < N) {
+        for (int dj = -1; dj <= 0; ++dj) {
+            const int jc = j + dj;
+            if (jc < 0 || jc > N - 2) continue;
+            const double xl = rxl[jc - (bj0 - 1)], xr = rxr[jc - (bj0 - 1)];
+            for (int di = -1; di <= 0; ++di) {
+                const int ic = i + di;
+                if (ic < 0 || ic > N - 2) continue;
+                vis |= (lattice_pos(C.x0, ic, C.hx) <= xr) && (lattice_pos(C.x0, ic + 1, C.hx) >= xl);
+            }
+        }
+    }
+    if (vis) atomicOr(&mbits[j - bj0], 1u << (i - bi0));
+    __syncthreads();
+    if (mask && t < BS && bj0 + t < N) {
+        const int halves = 2 * ((N + 31) / 32);
+        mask[(int64_t)(bj0 + t) * halves + bi0 / BS] = (uint16_t)mbits[t];
+    }
+    return vis;
+}
+
+// Cooperative block scan: every leaf whose centre is closer than its level's
+// radius to the block rectangle, in the fixed order (level, element, wave,
+// lane); indices with rank in [lo, lo + BCAP) go to bids.  Returns the total
+// count (block-uniform).  Every wave of the block must call it.
+__device__ int block_scan(const Tables& T, const Rect& r, int lo, int* bids, int* wcnt, int wave, int lane)
 {
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     int total = 0;
@@ -120,139 +176,234 @@ __device__ int scan_candidates(const Tables& T, const TileRect& r, int lo, float
         const float Rf = T.radius[l];
         if (!(Rf > 0.0f)) continue;
         const double R = Rf;
-        const double c = T.side / (double)(1 << l);
+        const double c = ldexp(T.side, -l), inv_c = ldexp(T.inv_side, l);
         const int S = 1 << l;
-        const int ia = max(0, (int)floor((r.x0 - R - T.x0) / c - 0.5));
-        const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) / c - 0.5));
-        const int ja = max(0, (int)floor((r.y0 - R - T.y0) / c - 0.5));
-        const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) / c - 0.5));
+        const int ia = max(0, (int)floor((r.x0 - R - T.x0) * inv_c - 0.5) - 1);
+        const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) * inv_c - 0.5) + 1);
+        const int ja = max(0, (int)floor((r.y0 - R - T.y0) * inv_c - 0.5) - 1);
+        const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) * inv_c - 0.5) + 1);
         const int wi = ib - ia + 1, hj = jb - ja + 1;
         if (wi <= 0 || hj <= 0) continue;
-        const int cnt = wi * hj;
+        const int cnt = __builtin_amdgcn_readfirstlane(wi * hj);
         const float inv_w = 1.0f / (float)wi;
-        const int64_t off = ((int64_t(1) << (2 * l)) - 1) / 3;
-        for (int e0 = 0; e0 < cnt; e0 += 64) {
-            const int e = e0 + lane;
-            int id = -1;
-            if (e < cnt) {
-                int q = (int)((float)e * inv_w);
-                int rem = e - q * wi;
-                if (rem < 0) { --q; rem += wi; }
-                if (rem >= wi) { ++q; rem -= wi; }
-                const int ii = ia + rem, jj = ja + q;
-                id = T.node[off + (int64_t)jj * S + ii];
-                if (id >= 0) {
-                    const double cx = T.x0 + (ii + 0.5) * c, cy = T.y0 + (jj + 0.5) * c;
-                    const double dx = fmax(fmax(r.x0 - cx, cx - r.x1), 0.0);
-                    const double dy = fmax(fmax(r.y0 - cy, cy - r.y1), 0.0);
-                    if (!(dx * dx + dy * dy < R * R) || id >= T.n) id = -1;
+        const int32_t* lvl = T.node + ((int64_t(1) << (2 * l)) - 1) / 3;
+        const double R2 = R * R;
+        for (int e0 = 0; e0 < cnt; e0 += 256 * UNROLL) {
+            int id[UNROLL], ii[UNROLL], jj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int e = e0 + u * 256 + (int)threadIdx.x;
+                id[u] = -1;
+                ii[u] = jj[u] = 0;
+                if (e < cnt) {
+                    int q = (int)((float)e * inv_w);
+                    int rem = e - q * wi;
+                    if (rem < 0) { --q; rem += wi; }
+                    if (rem >= wi) { ++q; rem -= wi; }
+                    ii[u] = ia + rem;
+                    jj[u] = ja + q;
+                    id[u] = lvl[(int64_t)jj[u] * S + ii[u]];
                 }
             }
-            const uint64_t m = __ballot(id >= 0);
-            if (m) {
-                const int slot = total + __popcll(m & lt) - lo;
-                if (id >= 0 && slot >= 0 && slot < CAP) {
-                    const float4 p = T.packed[id];
-                    rec[slot] = make_float4((float)((double)p.x - r.x0), (float)((double)p.y - r.y0), p.z, p.w);
-                    if (WITH_IDS) {
-                        ids[slot] = id;
-                        sig[slot] = T.sigma[id];
-                    }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                int v = id[u];
+                if (v >= 0) {
+                    const double cx = T.x0 + (ii[u] + 0.5) * c, cy = T.y0 + (jj[u] + 0.5) * c;
+                    const double dx = fmax(fmax(r.x0 - cx, cx - r.x1), 0.0);
+                    const double dy = fmax(fmax(r.y0 - cy, cy - r.y1), 0.0);
+                    if (!(dx * dx + dy * dy < R2) || v >= T.n) v = -1;
                 }
-                total += __popcll(m);
+                const uint64_t m = __ballot(v >= 0);
+                if (lane == 0) wcnt[wave] = __popcll(m);
+                __syncthreads();
+                int base = total, all = 0;
+#pragma unroll
+                for (int w = 0; w < WAVES; ++w) {
+                    const int k = wcnt[w];
+                    base += w < wave ? k : 0;
+                    all += k;
+                }
+                const int slot = base + __popcll(m & lt) - lo;
+                if (v >= 0 && slot >= 0 && slot < BCAP) bids[slot] = v;
+                total += all;
+                __syncthreads();
             }
         }
     }
     return total;
 }
 
-__global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C, Dom2 D, float* __restrict__ tex,
-                                                         uint32_t* __restrict__ mask)
+// Gathers the records of bids[0 .. nb) into brec as (s x, s y, s, v) relative
+// to the block origin (and sigma into bsig when given).
+__device__ inline void stage_block(const Tables& T, const Rect& r, const int* bids, int nb, float4* brec, float* bsig)
 {
-    __shared__ float4 rec_all[WAVES][CAP];
-    __shared__ double rxl[TS + 1], rxr[TS + 1];
-    __shared__ uint32_t mwords[TS];
+#pragma unroll
+    for (int u = 0; u < BCAP / 256; ++u) {
+        const int c = u * 256 + (int)threadIdx.x;
+        if (c < nb) {
+            const int id = bids[c];
+            const float4 p = T.packed[id];
+            const float xr = (float)((double)p.x - r.x0), yr = (float)((double)p.y - r.y0);
+            brec[c] = make_float4(xr * p.w, yr * p.w, p.w, p.z);
+            if (bsig) bsig[c] = T.sigma[id];
+        }
+    }
+}
+
+// True when record q (scaled) can reach the rectangle [x0, x1] x [y0, y1]
+// (coordinates relative to the block origin): its own truncation radius.
+__device__ inline bool reaches(const float4& q, float x0, float x1, float y0, float y1, float lim)
+{
+    const float dx = fmaxf(fmaxf(fmaf(x0, q.z, -q.x), fmaf(-x1, q.z, q.x)), 0.0f);
+    const float dy = fmaxf(fmaxf(fmaf(y0, q.z, -q.y), fmaf(-y1, q.z, q.y)), 0.0f);
+    return fmaf(dx, dx, dy * dy) < lim;
+}
+
+struct TileFrame {
+    float x0, x1, y0, y1;  // tile rectangle relative to the block origin
+    float npx, npy;        // minus the lane's texel centre relative to the block origin
+};
+
+__device__ inline TileFrame tile_frame(const TexCascade& C, const Dom2& D, const Rect& br, int ti0, int tj0, int i, int j)
+{
+    const Rect tr = texel_rect(C, D, ti0, tj0, TS, TS);
+    TileFrame f;
+    f.x0 = (float)(tr.x0 - br.x0);
+    f.x1 = (float)(tr.x1 - br.x0);
+    f.y0 = (float)(tr.y0 - br.y0);
+    f.y1 = (float)(tr.y1 - br.y0);
+    const int N = C.n;
+    f.npx = -(float)(clampd(lattice_pos(C.x0, min(i, N - 1), C.hx), D.x0, D.x1) - br.x0);
+    f.npy = -(float)(clampd(lattice_pos(C.y0, min(j, N - 1), C.hy), D.y0, D.y1) - br.y0);
+    return f;
+}
+
+__global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+                                                         float* __restrict__ tex, uint16_t* __restrict__ mask)
+{
+    __shared__ float4 brec[BCAP];
+    __shared__ int bids[BCAP];
+    __shared__ float4 trec_all[WAVES][TCAP];
+    __shared__ double rxl[BS + 1], rxr[BS + 1];
+    __shared__ uint32_t mbits[BS];
+    __shared__ int wcnt[WAVES];
+    __shared__ int any_vis;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int bi0 = blockIdx.x * (TS * WAVES), j0 = blockIdx.y * TS;
-    if (threadIdx.x <= TS) {
-        const int jc = j0 - 1 + (int)threadIdx.x;
-        double lo = INFINITY, hi = -INFINITY;
-        if (jc >= 0 && jc <= N - 2) strip_extent(C, lattice_pos(C.y0, jc, C.hy), lattice_pos(C.y0, jc + 1, C.hy), &lo, &hi);
-        rxl[threadIdx.x] = lo;
-        rxr[threadIdx.x] = hi;
-    }
-    if (threadIdx.x < TS) mwords[threadIdx.x] = 0u;
-    __syncthreads();
-    const int tx = lane & (TS - 1), ty = lane >> 3;
-    const int ti0 = bi0 + wave * TS;
-    const int i = ti0 + tx, j = j0 + ty;
+    int bx, by;
+    block_coords(gx, gy, &bx, &by);
+    const int bi0 = bx * BS, bj0 = by * BS;
+    const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
+    const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
     const bool inside = i < N && j < N;
-    const bool vis = inside && texel_visible(C, rxl, rxr, j0, i, j);
-    if (vis) atomicOr(&mwords[ty], 1u << (wave * TS + tx));
+    if (threadIdx.x == 0) any_vis = 0;
+    const bool vis = block_visibility(C, bi0, bj0, i, j, rxl, rxr, mbits, mask);
+    if (vis) any_vis = 1;
     __syncthreads();
-    if (mask && threadIdx.x < TS && j0 + (int)threadIdx.x < N)
-        mask[(int64_t)(j0 + threadIdx.x) * ((N + 31) / 32) + blockIdx.x] = mwords[threadIdx.x];
-    // from here on each wave works alone
-    if (__ballot(vis) == 0) {
+    if (!any_vis) {
         if (inside) tex[(int64_t)j * N + i] = -INFINITY;
         return;
     }
-    float4* rec = rec_all[wave];
-    const TileRect r = tile_rect(C, D, ti0, j0);
-    const float px = (float)(clampd(lattice_pos(C.x0, i, C.hx), D.x0, D.x1) - r.x0);
-    const float py = (float)(clampd(lattice_pos(C.y0, j, C.hy), D.y0, D.y1) - r.y0);
-    const float E = T.E;
-    float s0 = 0.0f, s1 = 0.0f;
-    for (int lo = 0;; lo += CAP) {
-        const int total = scan_candidates<false>(T, r, lo, rec, nullptr, nullptr, lane);
-        wave_sync();
-        const int nc = min(total - lo, CAP);
-        if (vis) {
-            int c = 0;
-            for (; c + 4 <= nc; c += 4) {
+    const Rect br = texel_rect(C, D, bi0, bj0, BS, BS);
+    const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j);
+    const bool tile_vis = __ballot(vis) != 0;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const float lim = T.T2 * 1.0001f, E = T.E;
+    float4* trec = trec_all[wave];
+    float s0 = 0.0f, s1 = 0.0f, vpart = 0.0f;
+    int n_eval = 0;
+    for (int lo = 0;; lo += BCAP) {
+        const int total = block_scan(T, br, lo, bids, wcnt, wave, lane);
+        const int nb = min(total - lo, BCAP);
+        stage_block(T, br, bids, nb, brec, nullptr);
+        __syncthreads();
+        if (tile_vis) {
+            int nt = 0;
+            for (int c0 = 0; c0 < nb; c0 += 64) {
+                const int c = c0 + lane;
+                const float4 q = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const bool keep = c < nb && reaches(q, f.x0, f.x1, f.y0, f.y1, lim);
+                const uint64_t m = __ballot(keep);
+                const int k = __popcll(m);
+                if (nt + k > TCAP) {  // evaluate the full chunk first
+                    wave_sync();
+                    for (int a = 0; a < nt; ++a) {
+                        const float4 r = trec[a];
+                        const float dx = fmaf(f.npx, r.z, r.x), dy = fmaf(f.npy, r.z, r.y);
+                        const float g = fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)), E);
+                        s0 += g;
+                        s1 = fmaf(g, r.w, s1);
+                    }
+                    n_eval += nt;
+                    nt = 0;
+                    wave_sync();
+                }
+                if (keep) {
+                    trec[nt + __popcll(m & lt)] = q;
+                    vpart += q.w;
+                }
+                nt += k;
+            }
+            wave_sync();
+            int a = 0;
+            for (; a + 4 <= nt; a += 4) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const float4 q = rec[c + u];
-                    const float dx = q.x - px, dy = q.y - py;
-                    const float g = __builtin_amdgcn_exp2f(q.w * fmaf(dx, dx, dy * dy));
-                    const float w = fmaxf(g - E, 0.0f);
-                    s0 += w;
-                    s1 = fmaf(w, q.z, s1);
+                    const float4 r = trec[a + u];
+                    const float dx = fmaf(f.npx, r.z, r.x), dy = fmaf(f.npy, r.z, r.y);
+                    const float g = fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)), E);
+                    s0 += g;
+                    s1 = fmaf(g, r.w, s1);
                 }
             }
-            for (; c < nc; ++c) {
-                const float4 q = rec[c];
-                const float dx = q.x - px, dy = q.y - py;
-                const float g = __builtin_amdgcn_exp2f(q.w * fmaf(dx, dx, dy * dy));
-                const float w = fmaxf(g - E, 0.0f);
-                s0 += w;
-                s1 = fmaf(w, q.z, s1);
+            for (; a < nt; ++a) {
+                const float4 r = trec[a];
+                const float dx = fmaf(f.npx, r.z, r.x), dy = fmaf(f.npy, r.z, r.y);
+                const float g = fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)), E);
+                s0 += g;
+                s1 = fmaf(g, r.w, s1);
             }
+            n_eval += nt;
+            wave_sync();
         }
-        wave_sync();
-        if (lo + CAP >= total) break;
+        if (lo + BCAP >= total) break;
+        __syncthreads();
     }
-    if (inside) tex[(int64_t)j * N + i] = vis ? (s0 > 0.0f ? s1 / s0 : NAN) : -INFINITY;
+    const float vsum = wave_sum(vpart);  // every lane of the wave takes part
+    if (!inside) return;
+    float out = -INFINITY;
+    if (vis) {
+        const float S0 = s0 - (float)n_eval * E;
+        const float S1 = s1 - E * vsum;
+        out = S0 > 0.0f ? S1 / S0 : NAN;
+    }
+    tex[(int64_t)j * N + i] = out;
 }
 
 // Adjoint of Eq. 2 / Eq. 1.  Lanes first own texels (S0 of each texel), then
-// own candidate leaves: for every texel of the tile with a non-zero gradient
+// own tile-list leaves: for every texel of the tile with a non-zero gradient
 // (a wave-uniform loop) each lane adds its leaf's share
 //   g w_j / S0   and   g (v_j - v_s) / S0 * exp(-q^2/2) q^2 / sigma_j,
 // and finally adds its two sums to the leaf's gradient with one atomic each.
-__global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D,
+__global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
                                                                   const float* __restrict__ tex,
                                                                   const float* __restrict__ gtex,
                                                                   float* __restrict__ gv, float* __restrict__ gs)
 {
-    __shared__ float4 rec_all[WAVES][CAP];
-    __shared__ int ids_all[WAVES][CAP];
-    __shared__ float sig_all[WAVES][CAP];
+    __shared__ float4 brec[BCAP];
+    __shared__ int bids[BCAP];
+    __shared__ float bsig[BCAP];
+    __shared__ unsigned short tidx_all[WAVES][BCAP];
+    __shared__ int wcnt[WAVES];
+    __shared__ int any_act;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ti0 = blockIdx.x * (TS * WAVES) + wave * TS, j0 = blockIdx.y * TS;
-    const int i = ti0 + (lane & (TS - 1)), j = j0 + (lane >> 3);
+    int bx, by;
+    block_coords(gx, gy, &bx, &by);
+    const int bi0 = bx * BS, bj0 = by * BS;
+    const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
+    const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
     const bool inside = i < N && j < N;
     float g = 0.0f, vs = 0.0f;
     if (inside) {
@@ -260,63 +411,91 @@ __global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexC
         vs = tex[(int64_t)j * N + i];
     }
     const bool act = inside && g != 0.0f && isfinite(vs) && isfinite(g);
+    if (threadIdx.x == 0) any_act = 0;
+    __syncthreads();
+    if (act) any_act = 1;
+    __syncthreads();
+    if (!any_act) return;
     const uint64_t active = __ballot(act);
-    if (active == 0) return;
-    float4* rec = rec_all[wave];
-    int* ids = ids_all[wave];
-    float* sig = sig_all[wave];
-    const TileRect r = tile_rect(C, D, ti0, j0);
-    const float px = (float)(clampd(lattice_pos(C.x0, i, C.hx), D.x0, D.x1) - r.x0);
-    const float py = (float)(clampd(lattice_pos(C.y0, j, C.hy), D.y0, D.y1) - r.y0);
-    const float E = T.E;
-    // pass 1: S0 per texel
+    const Rect br = texel_rect(C, D, bi0, bj0, BS, BS);
+    const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const float lim = T.T2 * 1.0001f, E = T.E;
+    unsigned short* tidx = tidx_all[wave];
+    // pass 1: S0 per texel (lanes own texels)
     float s0 = 0.0f;
-    for (int lo = 0;; lo += CAP) {
-        const int total = scan_candidates<true>(T, r, lo, rec, ids, sig, lane);
-        wave_sync();
-        const int nc = min(total - lo, CAP);
-        for (int c = 0; c < nc; ++c) {
-            const float4 q = rec[c];
-            const float dx = q.x - px, dy = q.y - py;
-            s0 += fmaxf(__builtin_amdgcn_exp2f(q.w * fmaf(dx, dx, dy * dy)) - E, 0.0f);
+    int total = 0;
+    for (int lo = 0;; lo += BCAP) {
+        total = block_scan(T, br, lo, bids, wcnt, wave, lane);
+        const int nb = min(total - lo, BCAP);
+        stage_block(T, br, bids, nb, brec, bsig);
+        __syncthreads();
+        if (active) {
+            for (int c0 = 0; c0 < nb; c0 += 64) {
+                const int c = c0 + lane;
+                const float4 q0 = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const bool keep = c < nb && reaches(q0, f.x0, f.x1, f.y0, f.y1, lim);
+                uint64_t m = __ballot(keep);
+                while (m) {
+                    const int t = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const float4 q = brec[c0 + t];
+                    const float dx = fmaf(f.npx, q.z, q.x), dy = fmaf(f.npy, q.z, q.y);
+                    s0 += fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)) - E, 0.0f);
+                }
+            }
         }
-        wave_sync();
-        if (lo + CAP >= total) break;
+        if (lo + BCAP >= total) break;
+        __syncthreads();
     }
     const float gn = act && s0 > 0.0f ? g / s0 : 0.0f;
-    // pass 2: lanes own candidates
-    for (int lo = 0;; lo += CAP) {
-        const int total = scan_candidates<true>(T, r, lo, rec, ids, sig, lane);
-        wave_sync();
-        const int nc = min(total - lo, CAP);
-        for (int c0 = 0; c0 < nc; c0 += 64) {
+    // pass 2: lanes own tile-list leaves; with a single round the block records are still staged
+    for (int lo = 0; lo < total; lo += BCAP) {
+        const int nb = min(total - lo, BCAP);
+        if (total > BCAP) {
+            __syncthreads();
+            block_scan(T, br, lo, bids, wcnt, wave, lane);
+            stage_block(T, br, bids, nb, brec, bsig);
+            __syncthreads();
+        }
+        if (!active) continue;
+        int nt = 0;
+        for (int c0 = 0; c0 < nb; c0 += 64) {
             const int c = c0 + lane;
-            const bool own = c < nc;
-            float4 q = own ? rec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-            const float sj = own ? sig[c] : 1.0f;
+            const float4 q = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const bool keep = c < nb && reaches(q, f.x0, f.x1, f.y0, f.y1, lim);
+            const uint64_t m = __ballot(keep);
+            if (keep) tidx[nt + __popcll(m & lt)] = (unsigned short)c;
+            nt += __popcll(m);
+        }
+        wave_sync();
+        for (int c0 = 0; c0 < nt; c0 += 64) {
+            const int a = c0 + lane;
+            const bool own = a < nt;
+            const int c = own ? tidx[a] : 0;
+            const float4 q = own ? brec[c] : make_float4(1e18f, 1e18f, 0.f, 0.f);
+            const float sj = own ? bsig[c] : 1.0f;
             float acc_v = 0.0f, acc_s = 0.0f;
             uint64_t m = active;
             while (m) {
                 const int t = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
-                const float tpx = __shfl(px, t), tpy = __shfl(py, t), tg = __shfl(gn, t), tv = __shfl(vs, t);
-                const float dx = q.x - tpx, dy = q.y - tpy;
-                const float r2 = fmaf(dx, dx, dy * dy);
-                const float ex = __builtin_amdgcn_exp2f(q.w * r2);
+                const float tnx = __shfl(f.npx, t), tny = __shfl(f.npy, t), tg = __shfl(gn, t), tv = __shfl(vs, t);
+                const float dx = fmaf(tnx, q.z, q.x), dy = fmaf(tny, q.z, q.y);
+                const float r2 = fmaf(dx, dx, dy * dy);  // (s r)^2 = q^2 log2(e) / 2
+                const float ex = __builtin_amdgcn_exp2f(-r2);
                 const float w = ex - E;
-                if (own && w > 0.0f) {
-                    const float q2 = r2 * q.w * (-2.0f / LOG2E);
+                if (w > 0.0f) {
                     acc_v = fmaf(tg, w, acc_v);
-                    acc_s = fmaf(tg * (q.z - tv), ex * q2 / sj, acc_s);
+                    acc_s = fmaf(tg * (q.w - tv), ex * r2 * (2.0f / LOG2E) / sj, acc_s);
                 }
             }
             if (own && (acc_v != 0.0f || acc_s != 0.0f)) {
-                atomicAdd(&gv[ids[c]], acc_v);
-                atomicAdd(&gs[ids[c]], acc_s);
+                atomicAdd(&gv[bids[c]], acc_v);
+                atomicAdd(&gs[bids[c]], acc_s);
             }
         }
         wave_sync();
-        if (lo + CAP >= total) break;
     }
 }
 
@@ -331,7 +510,8 @@ hfr_status tables_of(const hfr_leaves* L, bool backward, Tables* out)
     HFR_REQUIRE(std::isfinite(L->side) && L->side > 0 && std::isfinite(L->x0) && std::isfinite(L->y0),
                 "invalid lattice square");
     *out = Tables{reinterpret_cast<const float4*>(L->packed), L->level_radius, L->node, L->sigma, (int)L->n,
-                  L->max_depth, L->x0, L->y0, L->side, std::exp(-0.5f * L->cutoff * L->cutoff)};
+                  L->max_depth, L->x0, L->y0, L->side, 1.0 / L->side, std::exp(-0.5f * L->cutoff * L->cutoff),
+                  0.5f * LOG2E * L->cutoff * L->cutoff};
     return HFR_OK;
 }
 
@@ -368,11 +548,12 @@ extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom,
     HFR_REQUIRE(tex != nullptr, "tex is NULL");
     const int N = cas[0].n;
     const Dom2 D{dom->x0, dom->y0, dom->x1, dom->y1};
-    const dim3 grid((N + TS * WAVES - 1) / (TS * WAVES), (N + TS - 1) / TS);
+    const int gx = (N + BS - 1) / BS, gy = (N + BS - 1) / BS;
     const int words = (N + 31) / 32;
     for (int k = 0; k < K; ++k) {
-        discretize_kernel<<<grid, dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
-            T, tex_cascade(cas[k]), D, tex + (int64_t)k * N * N, mask ? mask + (int64_t)k * N * words : nullptr);
+        discretize_kernel<<<dim3(gx * gy), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
+            T, tex_cascade(cas[k]), D, gx, gy, tex + (int64_t)k * N * N,
+            mask ? reinterpret_cast<uint16_t*>(mask + (int64_t)k * N * words) : nullptr);
         HFR_LAUNCH_CHECK("discretize");
     }
     return hfr_ok();
@@ -390,10 +571,11 @@ extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_dom
     HFR_REQUIRE(tex && grad_tex && grad_v && grad_sigma, "NULL texture or gradient buffer");
     const int N = cas[0].n;
     const Dom2 D{dom->x0, dom->y0, dom->x1, dom->y1};
-    const dim3 grid((N + TS * WAVES - 1) / (TS * WAVES), (N + TS - 1) / TS);
+    const int gx = (N + BS - 1) / BS, gy = (N + BS - 1) / BS;
     for (int k = 0; k < K; ++k) {
-        discretize_backward_kernel<<<grid, dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
-            T, tex_cascade(cas[k]), D, tex + (int64_t)k * N * N, grad_tex + (int64_t)k * N * N, grad_v, grad_sigma);
+        discretize_backward_kernel<<<dim3(gx * gy), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
+            T, tex_cascade(cas[k]), D, gx, gy, tex + (int64_t)k * N * N, grad_tex + (int64_t)k * N * N, grad_v,
+            grad_sigma);
         HFR_LAUNCH_CHECK("discretize_backward");
     }
     return hfr_ok();
