@@ -216,13 +216,13 @@ __global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __
                                                       float* __restrict__ gtex)
 {
     const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
-    if (col >= A.W || row >= A.H) return;
+    const bool in_image = col < A.W && row < A.H;
+    if (!BACKWARD && !in_image) return;
     const int64_t p = (int64_t)row * A.W + col;
     float g = 0.0f;
-    if (BACKWARD) {
-        g = gdepth[p];
-        if (g == 0.0f || !isfinite(g)) return;
-    }
+    if (BACKWARD && in_image) g = gdepth[p];
+    // in the adjoint every lane stays to the end (the scatter uses wave-wide shuffles)
+    const bool live = in_image && (!BACKWARD || (g != 0.0f && isfinite(g)));
     const double sx = ((col + 0.5) / A.W) * 2.0 - 1.0;
     const double sy = 1.0 - ((row + 0.5) / A.H) * 2.0;
     Ray r;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __
     Hit HA, HB;
     HB.k = -1;
     bool found = false;
-    if (tin < tout) {
+    if (live && tin < tout) {
         const double dd = r.d[0] * A.c[0].vx + r.d[1] * A.c[0].vy;
         const bool fwd = dd >= 0.0;
         for (int s = 0; s < A.K && !found; ++s) {
@@ -298,19 +298,58 @@ __global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __
         hit[p] = hid;
         return;
     }
-    if (!found) return;
+    // gradient scatter: wave-combined for lanes that share a cell (common near
+    // the camera, where many pixels land in one texture cell), direct atomics
+    // for the rest
     const int N = A.N;
     for (int x = 0; x < 2; ++x) {
         const Hit& H = x ? HB : HA;
         const double cf = x ? cB : cA;
-        if (H.k < 0 || H.start || !(H.fp < 0.0) || cf == 0.0) continue;
-        const double s = (double)g * cf / H.fp;
-        float* gk = gtex + (int64_t)H.k * N * N;
-        const double u = H.u, v = H.v;
-        atomicAdd(&gk[(int64_t)H.j * N + H.i], (float)(s * (1.0 - u) * (1.0 - v)));
-        atomicAdd(&gk[(int64_t)H.j * N + H.i + 1], (float)(s * u * (1.0 - v)));
-        atomicAdd(&gk[(int64_t)(H.j + 1) * N + H.i], (float)(s * (1.0 - u) * v));
-        atomicAdd(&gk[(int64_t)(H.j + 1) * N + H.i + 1], (float)(s * u * v));
+        const bool has = found && H.k >= 0 && !H.start && H.fp < 0.0 && cf != 0.0;
+        float w[4] = {0.f, 0.f, 0.f, 0.f};
+        int key = -1;
+        if (has) {
+            const double sc = (double)g * cf / H.fp;
+            const double u = H.u, v = H.v;
+            w[0] = (float)(sc * (1.0 - u) * (1.0 - v));
+            w[1] = (float)(sc * u * (1.0 - v));
+            w[2] = (float)(sc * (1.0 - u) * v);
+            w[3] = (float)(sc * u * v);
+            key = (H.k << 26) | (H.j << 13) | H.i;
+        }
+        const int lane = __lane_id();  // hardware lane: the workgroup is 2-D, threadIdx.x is only the column
+        uint64_t pending = __ballot(has);
+        for (int it = 0; it < 4 && pending; ++it) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int lkey = __shfl(key, leader);
+            const uint64_t match = __ballot(has && key == lkey) & pending;
+            if (__popcll(match) < 4) break;  // little sharing left: plain atomics are cheaper
+            const bool mine = (match >> lane) & 1;
+            float sum[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float t = mine ? w[c] : 0.0f;
+                for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+                sum[c] = t;
+            }
+            if (lane == leader) {
+                float* gk = gtex + (int64_t)(lkey >> 26) * N * N;
+                const int64_t b = (int64_t)((lkey >> 13) & 8191) * N + (lkey & 8191);
+                atomicAdd(&gk[b], sum[0]);
+                atomicAdd(&gk[b + 1], sum[1]);
+                atomicAdd(&gk[b + N], sum[2]);
+                atomicAdd(&gk[b + N + 1], sum[3]);
+            }
+            pending &= ~match;
+        }
+        if (has && ((pending >> lane) & 1)) {
+            float* gk = gtex + (int64_t)H.k * N * N;
+            const int64_t b = (int64_t)H.j * N + H.i;
+            atomicAdd(&gk[b], w[0]);
+            atomicAdd(&gk[b + 1], w[1]);
+            atomicAdd(&gk[b + N], w[2]);
+            atomicAdd(&gk[b + N + 1], w[3]);
+        }
     }
 }
 
