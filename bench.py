@@ -10,6 +10,7 @@ before timing.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -23,6 +24,28 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+
+
+def recorded_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch from a committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a copy of known
+    size).  The figure is only valid for the kernel source it was taken on,
+    so it is returned only when the summary's recorded SHA-256 matches."""
+    try:
+        with open(os.path.join(ROOT, summary)) as f:
+            text = f.read()
+        with open(os.path.join(ROOT, kernel_source), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.lstrip("- `").split(":")[0] in ("source_sha256", "traffic_bytes_per_launch"):
+            k, v = line.lstrip("- `").split(":", 1)
+            fields[k] = v.strip().strip("`")
+    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def build_scene(name: str):
@@ -247,7 +270,11 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(work["bytes"] / t_disc / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(t_hbm_floor / t_disc, 4)}
-    roof.update({"traffic": None, "kernel": "discretize_kernel", "launches": K,
+    traffic = None
+    if args.workload == "medium":
+        traffic = recorded_traffic("paper_2201_10887_amd/csrc/hfr_discretize.hip",
+                                   "profiles/discretize_kernel_medium_hbm_counters.md")
+    roof.update({"traffic": traffic, "kernel": "discretize_kernel", "launches": K,
                  "per_launch_ms": round(stage_ms["discretize"] / K, 4),
                  "algorithmic_flops_per_launch": round(work["flops"] / K), "algorithmic_bytes_per_launch":
                  round(work["bytes"] / K), "hbm_frac": round(t_hbm_floor / t_disc, 4),

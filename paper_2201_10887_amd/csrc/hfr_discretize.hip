@@ -60,20 +60,29 @@ struct Rect {
     double x0, y0, x1, y1;
 };
 
+// Packs leaf records and finds, per quadtree level, the largest support
+// radius.  The per-level maxima are reduced in LDS first so that each block
+// issues at most max_depth + 1 global atomics (one per level it saw).
 __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restrict__ x, const float* __restrict__ y,
                                                           const float* __restrict__ v, const float* __restrict__ c,
                                                           const float* __restrict__ sigma, float cutoff, float side,
                                                           int max_depth, float4* __restrict__ out,
                                                           float* __restrict__ radius, int64_t n)
 {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    const float sc = sigma[a] * c[a];
-    out[a] = make_float4(x[a], y[a], v[a], sqrtf(HALF_LOG2E) / sc);
-    int l = (int)rintf(log2f(side / c[a]));
-    l = min(max(l, 0), max_depth);
-    const float R = cutoff * sc * 1.00001f;
-    atomicMax(reinterpret_cast<int*>(radius) + l, __float_as_int(R));  // positive floats order as ints
+    __shared__ int level_max[16];  // max_depth <= 15; positive floats order as ints, 0 = no leaf seen
+    if (threadIdx.x < 16) level_max[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+        const float sc = sigma[a] * c[a];
+        out[a] = make_float4(x[a], y[a], v[a], sqrtf(HALF_LOG2E) / sc);
+        int l = (int)rintf(log2f(side / c[a]));
+        l = min(max(l, 0), max_depth);
+        const float R = cutoff * sc * 1.00001f;
+        atomicMax(&level_max[l], __float_as_int(R));
+    }
+    __syncthreads();
+    if (threadIdx.x <= (unsigned)max_depth && level_max[threadIdx.x] != 0)
+        atomicMax(reinterpret_cast<int*>(radius) + threadIdx.x, level_max[threadIdx.x]);
 }
 
 __global__ void zero_floats_kernel(float* __restrict__ p, int n)
@@ -529,7 +538,7 @@ extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
     hipStream_t s = (hipStream_t)stream;
     zero_floats_kernel<<<1, 64, 0, s>>>(L->level_radius, L->max_depth + 1);
     HFR_LAUNCH_CHECK("pack_leaves (radius reset)");
-    const int64_t blocks = (L->n + 255) / 256;
+    const int64_t blocks = std::min<int64_t>((L->n + 255) / 256, 2048);
     pack_leaves_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
         L->x, L->y, L->v, L->c, L->sigma, L->cutoff, (float)L->side, L->max_depth,
         reinterpret_cast<float4*>(L->packed), L->level_radius, L->n);
