@@ -184,6 +184,132 @@ def cpu_baseline(w, leaves, cam, R, cas, vis_texels, seconds=12.0):
                       f"{cam.width}x{cam.height} rays"}
 
 
+def fit_tau(dem, side, depth, target, rel=0.15, iters=24):
+    """Refinement threshold (bisected on a log scale) whose quadtree has about ``target`` leaves."""
+    from paper_2201_10887_amd import api
+    lo, hi, best = 1e-3, 1e3, None
+    for _ in range(iters):
+        tau = math.sqrt(lo * hi)
+        n = api.quadtree_leaf_count(dem, side, depth, tau)
+        if best is None or abs(n - target) < abs(best[1] - target):
+            best = (tau, n)
+        if abs(n - target) <= rel * target:
+            break
+        if n > target:
+            lo = tau
+        else:
+            hi = tau
+    return best[0]
+
+
+def build_batch_scene(n_fields=8, n_views=64, seed=1004, budget_texels=1 << 28):
+    """8 fBm heightfields of uneven size and 64 views of them (seeded)."""
+    from paper_2201_10887_amd import api, autotune, synth
+    from paper_2201_10887_amd.batch import BatchRenderer, Field, ViewSpec
+    t0 = time.time()
+    fspecs = synth.batch_fields(n_fields, seed)
+    vspecs = synth.batch_views(n_views, n_fields, seed)
+    dems, fields = [], []
+    for f in fspecs:
+        dem = synth.fbm_dem(f.dem_n, f.octaves, 0.8, f.seed)
+        tau = fit_tau(dem, f.side, f.depth, f.target_leaves)
+        leaves = api.build_quadtree(dem, f.side, f.depth, tau)
+        leaves["sigma"] = np.ones(len(leaves["x"]), np.float32)
+        dems.append(dem)
+        fields.append(Field(leaves, f.side, f.depth, 3.5))
+    cams = synth.batch_cameras(dems, fspecs, vspecs, seed)
+    ns = autotune.texel_budget([(v.width, v.height, v.K) for v in vspecs], budget_texels)
+    specs = [ViewSpec(v.field, v.K, n, v.width, v.height, 0.5, 0.05) for v, n in zip(vspecs, ns)]
+    R = BatchRenderer(fields, specs, backward=True)
+    R.set_cameras(cams)
+    print(f"[bench] batch scene: {n_fields} fields ({', '.join(str(f.n) for f in fields)} leaves), {n_views} views, "
+          f"{sum(s.K * s.N * s.N for s in specs)} texels, built in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    return R, cams
+
+
+def batch_main(args):
+    """Many views of many heightfields: one batched launch set (captured as a graph) against
+    the same views rendered one by one through the per-view entry points."""
+    import torch
+    from paper_2201_10887_amd import api, autotune
+    R, cams = build_batch_scene()
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda").manual_seed(1004)
+    R.forward()
+    for b in R.bufs:
+        d = b["depth"]
+        b["grad_depth"].copy_(torch.where(torch.isfinite(d), torch.randn(d.shape, generator=gen, device="cuda"),
+                                          torch.zeros_like(d)))
+    tuned = autotune.tune(R, cams, backward=True,
+                          log=lambda m: print(m, file=sys.stderr, flush=True) if args.verbose else None)
+    print(f"[bench] tuning {tuned['tuning']} ({'cached' if tuned['cached'] else 'measured'})", file=sys.stderr,
+          flush=True)
+
+    def train():
+        R.forward()
+        R.backward()
+
+    for _ in range(args.warmup):
+        train()
+    ms = {"batch_fwd": timed(R.forward, args.steps, stream), "batch_fwd_bwd": timed(train, args.steps, stream)}
+    g_fwd, g_train = R.capture(backward=False), R.capture(backward=True)
+    ms["graph_fwd"] = timed(g_fwd.replay, args.steps, stream)
+    ms["graph_fwd_bwd"] = timed(g_train.replay, args.steps, stream)
+
+    cas = [R.cascades(v) for v in range(R.n_views)]
+
+    def per_view_fwd():
+        for v, b in enumerate(R.bufs):
+            f = R.fields[R.specs[v].field]
+            api.discretize(f.L, f.dom, cas[v], b["tex"])
+            api.build_maxmip(b["tex"], b["mip"])
+            api.raycast(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["depth"], b["hit"])
+
+    def per_view_train():
+        for f in R.fields:
+            f.grad_v.zero_()
+            f.grad_sigma.zero_()
+        for v, b in enumerate(R.bufs):
+            f = R.fields[R.specs[v].field]
+            api.discretize(f.L, f.dom, cas[v], b["tex"])
+            api.build_maxmip(b["tex"], b["mip"])
+            api.raycast(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["depth"], b["hit"])
+            b["grad_tex"].zero_()
+            api.raycast_backward(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["grad_depth"], b["grad_tex"])
+            api.discretize_backward(f.L, f.dom, cas[v], b["tex"], b["grad_tex"], f.grad_v, f.grad_sigma)
+
+    per_view_train()
+    ms["per_view_fwd"] = timed(per_view_fwd, args.steps, stream)
+    ms["per_view_fwd_bwd"] = timed(per_view_train, args.steps, stream)
+    texels = sum(s.K * s.N * s.N for s in R.specs)
+    rays = sum(s.width * s.height for s in R.specs)
+    out = {
+        "metric": "batched views: ms per batch step (forward + backward), vs the same views rendered one by one",
+        "value": round(ms["graph_fwd_bwd"], 4),
+        "unit": "ms/batch",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms["graph_fwd_bwd"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 texels, f64 ray geometry",
+        "data": "synthetic (seeded fBm terrain)",
+        "config": {"workload": "batch: 8 fBm heightfields (10k-1.5M leaves, depth 8-12), 64 views "
+                               "(256^2 to 1080p, K 2-4, texel budget 2^28)",
+                   "fields": [f.n for f in R.fields], "views": R.n_views, "texels": texels, "rays": rays},
+        "ms": {k: round(v, 4) for k, v in ms.items()},
+        "speedup_vs_per_view": {"fwd": round(ms["per_view_fwd"] / ms["graph_fwd"], 3),
+                                "fwd_bwd": round(ms["per_view_fwd_bwd"] / ms["graph_fwd_bwd"], 3)},
+        "grays_per_s_fwd": round(rays / (ms["graph_fwd"] * 1e-3) / 1e9, 3),
+        "tuning": tuned["tuning"],
+        "tuning_cached": tuned["cached"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +318,7 @@ def main():
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (known traffic) to calibrate hardware byte counters")
     args = ap.parse_args()
@@ -200,6 +327,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        return batch_main(args)
     import torch
     from paper_2201_10887_amd import api, synth
     from paper_2201_10887_amd.renderer import Renderer

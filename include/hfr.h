@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 2
+#define HFR_ABI_VERSION 3
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -272,6 +272,115 @@ hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
                                    const hfr_cascade* cas, int32_t K, const float* tex,
                                    const float* grad_tex, float* grad_v, float* grad_sigma,
                                    hfr_stream stream);
+
+/* ------------------------------------------------------------- batching
+ *
+ * Many views (camera + cascade set) of many heightfields rendered by one
+ * set of launches: discretize (one persistent launch for every cascade of
+ * every view), max-mipmap (one launch per five-level pass), ray casting
+ * (one persistent launch for every pixel of every view), and for the
+ * backward pass the two adjoints (one persistent launch each).  Persistent
+ * workgroups take work from per-XCD queues and steal from other queues when
+ * theirs is empty, so views of uneven size share the GPU without a launch
+ * per view.  The per-view work is the same as hfr_discretize,
+ * hfr_build_maxmip and hfr_raycast (bit-identical outputs) and their
+ * adjoints; the batch is not in the paper, which renders one view per frame.
+ *
+ * The plan is a library-owned host object holding device copies of the
+ * field and view descriptors (allocated by hfr_batch_plan_create, the only
+ * call that allocates); every buffer it names stays caller-owned and must
+ * outlive the plan.  hfr_batch_launch and hfr_batch_launch_backward
+ * allocate nothing, issue no memset and no host synchronisation, and read
+ * every per-camera value from device memory, so both may be captured into
+ * one HIP graph and replayed after hfr_batch_set_cameras has changed the
+ * cameras.  A plan is not thread-safe, and launches of one plan on
+ * different streams race on its queues. */
+
+typedef struct hfr_batch_plan hfr_batch_plan;
+
+/* One heightfield.  leaves: as for hfr_discretize (packed records, level
+ * radii and node table already built; sigma is needed for the backward
+ * pass).  dom: its domain.  grad_v, grad_sigma: device float[leaves.n]
+ * written by hfr_batch_launch_backward (summed over every view of this
+ * field), or NULL when the plan has no backward pass. */
+typedef struct {
+    hfr_leaves leaves;
+    hfr_domain dom;
+    float* grad_v;
+    float* grad_sigma;
+} hfr_batch_field;
+
+/* One view of field `field`: K cascades of N x N texels (N a power of two in
+ * [2, HFR_MAX_TEX_N]) and a width x height image.  split_lambda, overlap,
+ * c_min: as for hfr_fit_cascades.  Device buffers: tex float[K][N][N]; mask uint32
+ * [K][N][(N+31)/32] or NULL; mip float[K][(4N^2-1)/3]; depth float[H][W];
+ * hit int32[H][W]; for the backward pass grad_depth float[H][W] (read) and
+ * grad_tex float[K][N][N] (scratch of the plan's backward pass, overwritten),
+ * or both NULL. */
+typedef struct {
+    int32_t field;
+    int32_t K, N;
+    int32_t width, height;
+    double split_lambda, overlap, c_min;
+    float* tex;
+    uint32_t* mask;
+    float* mip;
+    float* depth;
+    int32_t* hit;
+    const float* grad_depth;
+    float* grad_tex;
+} hfr_batch_view;
+
+/* Launch shape.  disc_blocks_per_cu, ray_blocks_per_cu: persistent
+ * workgroups (256 threads) per compute unit for the discretize kernels and
+ * the ray-cast kernels, in [1, 16].  ray_tile_w: width of the 64-pixel tile
+ * a wave takes at a time (8, 16, 32 or 64; height 64 / ray_tile_w).
+ * Defaults: 4, 4, 8. */
+typedef struct {
+    int32_t disc_blocks_per_cu;
+    int32_t ray_blocks_per_cu;
+    int32_t ray_tile_w;
+} hfr_batch_tuning;
+
+/* Validates the fields and views, copies their descriptors to device memory
+ * and returns a plan (*out).  Cameras must be set (hfr_batch_set_cameras)
+ * before the first launch.  EINVAL: n_fields or n_views outside [1, 4096],
+ * a view naming a missing field, K, N or image size out of range, NULL
+ * buffers, or a total work count above 2^31.  ENOMEM / EDEVICE: allocation
+ * failures.  Synchronous. */
+hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32_t n_fields, const hfr_batch_view* views,
+                                 int32_t n_views, hfr_batch_plan** out);
+void hfr_batch_plan_destroy(hfr_batch_plan* plan);
+
+/* Sets the launch shape (synchronous: not to be captured; a graph captured
+ * before it must be captured again).  EINVAL on values outside the ranges
+ * above. */
+hfr_status hfr_batch_set_tuning(hfr_batch_plan* plan, const hfr_batch_tuning* tuning);
+
+/* Fits the cascades of every view to its camera (hfr_fit_cascades, host)
+ * and enqueues the upload of the per-view descriptors on `stream` (from a
+ * plan-owned pinned buffer; the call first waits for its previous upload
+ * to finish).  cams: host hfr_camera[n_views], each with the view's width
+ * and height.  EINVAL as hfr_fit_cascades, or a camera whose image size
+ * differs from its view's. */
+hfr_status hfr_batch_set_cameras(hfr_batch_plan* plan, const hfr_camera* cams, hfr_stream stream);
+
+/* Copies view `view`'s cascades from the last hfr_batch_set_cameras into the
+ * host array out[K]. */
+hfr_status hfr_batch_cascades(const hfr_batch_plan* plan, int32_t view, hfr_cascade* out);
+
+/* Forward pass of every view: textures, masks, max-mipmaps, depth and hit
+ * images, as hfr_discretize + hfr_build_maxmip + hfr_raycast would write
+ * them view by view. */
+hfr_status hfr_batch_launch(const hfr_batch_plan* plan, hfr_stream stream);
+
+/* Backward pass of every view, after hfr_batch_launch: zeroes every view's
+ * grad_tex and every field's grad_v / grad_sigma, then writes the gradient
+ * of sum over views of sum(grad_depth * depth) with respect to the leaf
+ * values and Gaussian widths (hfr_raycast_backward and
+ * hfr_discretize_backward per view, summed per field).  EINVAL when a view
+ * or field lacks its gradient buffers. */
+hfr_status hfr_batch_launch_backward(const hfr_batch_plan* plan, hfr_stream stream);
 
 #ifdef __cplusplus
 }

@@ -52,6 +52,24 @@ class Leaves(ctypes.Structure):
                 ("side", ctypes.c_double)]
 
 
+class BatchField(ctypes.Structure):
+    _fields_ = [("leaves", Leaves), ("dom", Domain), ("grad_v", ctypes.c_void_p), ("grad_sigma", ctypes.c_void_p)]
+
+
+class BatchView(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_int32), ("K", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("split_lambda", ctypes.c_double), ("overlap", ctypes.c_double), ("c_min", ctypes.c_double),
+                ("tex", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("mip", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("hit", ctypes.c_void_p), ("grad_depth", ctypes.c_void_p),
+                ("grad_tex", ctypes.c_void_p)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("disc_blocks_per_cu", ctypes.c_int32), ("ray_blocks_per_cu", ctypes.c_int32),
+                ("ray_tile_w", ctypes.c_int32)]
+
+
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
 I64 = ctypes.c_int64
@@ -79,6 +97,13 @@ SIGNATURES = {
     "hfr_raycast": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P], I32),
     "hfr_raycast_backward": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P], I32),
     "hfr_discretize_backward": ([PP(Leaves), PP(Domain), PP(Cascade), I32, P, P, P, P, P], I32),
+    "hfr_batch_plan_create": ([PP(BatchField), I32, PP(BatchView), I32, PP(P)], I32),
+    "hfr_batch_plan_destroy": ([P], None),
+    "hfr_batch_set_tuning": ([P, PP(BatchTuning)], I32),
+    "hfr_batch_set_cameras": ([P, PP(Camera), P], I32),
+    "hfr_batch_cascades": ([P, I32, PP(Cascade)], I32),
+    "hfr_batch_launch": ([P, P], I32),
+    "hfr_batch_launch_backward": ([P, P], I32),
 }
 
 _lib = None

@@ -116,6 +116,19 @@ def build_quadtree(dem: np.ndarray, side: float, max_depth: int, tau: float, x0:
     return out
 
 
+def quadtree_leaf_count(dem: np.ndarray, side: float, max_depth: int, tau: float) -> int:
+    """Leaf count of ``build_quadtree`` without exporting the leaves."""
+    dem = np.ascontiguousarray(dem, np.float32)
+    q = ctypes.c_void_p()
+    call("hfr_build_quadtree", _np_ptr(dem), dem.shape[0], side, 0.0, 0.0, max_depth, tau, ctypes.byref(q))
+    try:
+        n = ctypes.c_int64()
+        call("hfr_quadtree_size", q, ctypes.byref(n))
+        return int(n.value)
+    finally:
+        _lib.load().hfr_quadtree_destroy(q)
+
+
 def build_neighbours(leaves: dict, side: float, max_depth: int, cutoff: float, slack: float = 1e-3,
                      x0: float = 0.0, y0: float = 0.0) -> tuple:
     arrs = [np.ascontiguousarray(leaves[k], np.float32) for k in ("x", "y", "c", "sigma")]
@@ -251,3 +264,86 @@ def discretize_backward(L: DeviceLeaves, dom, cascades: ctypes.Array, tex, grad_
          _dev(grad_v, torch.float32, (L.n,), "grad_v"), _dev(grad_sigma, torch.float32, (L.n,), "grad_sigma"),
          _stream(stream))
     return grad_v, grad_sigma
+
+
+# ------------------------------------------------------------------ batching
+
+class BatchPlan:
+    """Handle of an ``hfr_batch_plan`` plus references to every tensor it names
+    (the plan stores raw device pointers, so the tensors must stay alive)."""
+
+    def __init__(self, handle: ctypes.c_void_p, keep: list, n_views: int, ks: list):
+        self.handle, self._keep, self.n_views, self.ks = handle, keep, n_views, ks
+
+    def __del__(self):
+        batch_plan_destroy(self)
+
+
+def batch_plan_create(fields: Sequence[dict], views: Sequence[dict]) -> BatchPlan:
+    """``fields``: dicts with ``leaves`` (DeviceLeaves), ``dom`` and optional ``grad_v`` /
+    ``grad_sigma`` (float32 [n]).  ``views``: dicts with ``field, K, N, width, height,
+    split_lambda, overlap, c_min, tex, mip, depth, hit`` and optional ``mask, grad_depth,
+    grad_tex`` (shapes as for the per-view entry points)."""
+    import torch
+    keep = []
+    farr = (_lib.BatchField * len(fields))()
+    for a, f in enumerate(fields):
+        L = f["leaves"]
+        farr[a].leaves = L.struct()
+        farr[a].dom = domain(f["dom"])
+        for name in ("grad_v", "grad_sigma"):
+            t = f.get(name)
+            setattr(farr[a], name, _dev(t, torch.float32, (L.n,), name).value if t is not None else None)
+            keep.append(t)
+        keep.append(L)
+    varr = (_lib.BatchView * len(views))()
+    for a, v in enumerate(views):
+        K, N, W, H = int(v["K"]), int(v["N"]), int(v["width"]), int(v["height"])
+        b = varr[a]
+        b.field, b.K, b.N, b.width, b.height = int(v["field"]), K, N, W, H
+        b.split_lambda, b.overlap, b.c_min = float(v["split_lambda"]), float(v["overlap"]), float(v["c_min"])
+        b.tex = _dev(v["tex"], torch.float32, (K, N, N), "tex").value
+        b.mip = _dev(v["mip"], torch.float32, (K, mip_size(N)), "mip").value
+        b.depth = _dev(v["depth"], torch.float32, (H, W), "depth").value
+        b.hit = _dev(v["hit"], torch.int32, (H, W), "hit").value
+        m, gd, gt = v.get("mask"), v.get("grad_depth"), v.get("grad_tex")
+        b.mask = _dev(m, torch.int32, (K, N, (N + 31) // 32), "mask").value if m is not None else None
+        b.grad_depth = _dev(gd, torch.float32, (H, W), "grad_depth").value if gd is not None else None
+        b.grad_tex = _dev(gt, torch.float32, (K, N, N), "grad_tex").value if gt is not None else None
+        keep.extend([v["tex"], v["mip"], v["depth"], v["hit"], m, gd, gt])
+    handle = ctypes.c_void_p()
+    call("hfr_batch_plan_create", farr, len(fields), varr, len(views), ctypes.byref(handle))
+    return BatchPlan(handle, keep, len(views), [int(v["K"]) for v in views])
+
+
+def batch_plan_destroy(plan: BatchPlan) -> None:
+    if getattr(plan, "handle", None) is not None and plan.handle.value:
+        _lib.load().hfr_batch_plan_destroy(plan.handle)
+        plan.handle = None
+
+
+def batch_set_tuning(plan: BatchPlan, disc_blocks_per_cu: int = 4, ray_blocks_per_cu: int = 4,
+                     ray_tile_w: int = 8) -> None:
+    t = _lib.BatchTuning(int(disc_blocks_per_cu), int(ray_blocks_per_cu), int(ray_tile_w))
+    call("hfr_batch_set_tuning", plan.handle, ctypes.byref(t))
+
+
+def batch_set_cameras(plan: BatchPlan, cams: Sequence, stream=None) -> None:
+    arr = (Camera * len(cams))(*[camera(c) for c in cams])
+    if len(cams) != plan.n_views:
+        raise ValueError(f"{len(cams)} cameras for {plan.n_views} views")
+    call("hfr_batch_set_cameras", plan.handle, arr, _stream(stream))
+
+
+def batch_cascades(plan: BatchPlan, view: int) -> ctypes.Array:
+    out = (Cascade * plan.ks[view])()
+    call("hfr_batch_cascades", plan.handle, int(view), out)
+    return out
+
+
+def batch_launch(plan: BatchPlan, stream=None) -> None:
+    call("hfr_batch_launch", plan.handle, _stream(stream))
+
+
+def batch_launch_backward(plan: BatchPlan, stream=None) -> None:
+    call("hfr_batch_launch_backward", plan.handle, _stream(stream))

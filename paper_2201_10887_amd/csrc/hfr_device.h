@@ -103,3 +103,125 @@ inline hfr_status check_domain(const hfr_domain* dom)
     HFR_REQUIRE(dom->x1 > dom->x0 && dom->y1 > dom->y0 && dom->zmax >= dom->zmin, "empty domain");
     return HFR_OK;
 }
+
+// Texture-domain rectangle used by the texture kernels.
+struct Dom2 {
+    double x0, y0, x1, y1;
+};
+
+// Leaf data and constants of one heightfield, as the texture kernels read them.
+struct Tables {
+    const float4* packed;
+    const float* radius;
+    const int32_t* node;
+    const float* sigma;
+    int n, max_depth;
+    double x0, y0, side, inv_side;
+    float E;   // exp(-cutoff^2 / 2)
+    float T2;  // (s r)^2 at the truncation radius: cutoff^2 log2(e) / 2
+};
+
+// Per-cascade ray-cast constants.
+struct RayCas {
+    double near_d, far_d, split_d, ox, oy, vx, vy, x0, y0, hx, hy, inv_hx, inv_hy;
+    int n, levels;
+};
+
+// Everything a ray-cast kernel needs about one view.
+struct RayArgs {
+    double o[3], fwd[3], right[3], up[3];
+    double tx, ty;
+    int W, H, K, N;
+    double X0, Y0, X1, Y1, zmax;
+    RayCas c[HFR_MAX_CASCADES];
+};
+
+hfr_status leaf_tables(const hfr_leaves* L, bool backward, Tables* out);
+hfr_status ray_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K, RayArgs* A);
+
+// ---------------------------------------------------------------- batching
+// Device-resident descriptors of a batch plan.
+
+struct BatchField {
+    Tables T;
+    Dom2 D;
+    float* gv;
+    float* gs;
+};
+
+// One cascade of one view.
+struct BatchTex {
+    TexCascade C;
+    int field, gx;  // gx x gx blocks of 16 x 16 texels
+    float* tex;     // this cascade's texture, mask, pyramid and texel gradients
+    uint16_t* mask;
+    float* mip;
+    float* gtex;
+};
+
+struct BatchView {
+    RayArgs A;
+    const float* tex;  // the view's [K][N][N] textures and [K][(4N^2-1)/3] pyramids
+    const float* mip;
+    float* depth;
+    int32_t* hit;
+    const float* gdepth;
+    float* gtex;
+    int tiles_x;       // 64-pixel tiles per image row
+};
+
+constexpr int HFR_QUEUE_DISC = 0, HFR_QUEUE_RAY = 8, HFR_QUEUE_RAY_BWD = 16, HFR_QUEUE_DISC_BWD = 24;
+constexpr int HFR_QUEUE_WORDS = 32;
+constexpr int HFR_MIP_PASSES = 3;  // ceil(log2(HFR_MAX_TEX_N) / 5)
+
+struct BatchDev {
+    const BatchField* fields;
+    const BatchTex* tex;
+    const int* tex_start;  // [n_tex + 1] prefix sums of 16 x 16 texel blocks
+    const int* mip_start;  // [HFR_MIP_PASSES][n_tex + 1] prefix sums of max-mipmap blocks per pass
+    const BatchView* views;
+    const int* ray_start;  // [n_views + 1] prefix sums of 64-pixel tiles
+    int* queues;           // HFR_QUEUE_WORDS counters, zeroed before each persistent launch
+    int n_tex, n_views, tile_w;
+};
+
+hfr_status launch_discretize_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s);
+hfr_status launch_maxmip_batch(const BatchDev& P, const int* pass_blocks, hipStream_t s);
+hfr_status launch_raycast_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s);
+
+// Next range of work indices from a set of 8 queues that split [0, total)
+// into 8 contiguous chunks, one per XCD (the hardware deals workgroups to
+// the XCDs round-robin, so blockIdx.x & 7 names the workgroup's XCD; a
+// wrong guess only costs locality).  A caller starts with its own chunk and
+// moves to the next ones when it is exhausted, taking up to `grain`
+// consecutive indices per atomic: [*w0, *w1).  False when all queues are
+// exhausted.  Each counter only grows, so every caller ends after at most 8
+// failed attempts.
+__device__ inline bool queue_grab(int* q, int total, int xcd, int grain, int* w0, int* w1)
+{
+    for (int a = 0; a < 8; ++a) {
+        const int c = (xcd + a) & 7;
+        const int lo = (int)((int64_t)total * c / 8), hi = (int)((int64_t)total * (c + 1) / 8);
+        if (lo >= hi || __hip_atomic_load(&q[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo) continue;
+        const int idx = lo + atomicAdd(&q[c], grain);
+        if (idx < hi) {
+            *w0 = idx;
+            *w1 = min(idx + grain, hi);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Item holding work index w: the i with start[i] <= w < start[i + 1]
+// (start[0] = 0, start[n] > w; empty items are skipped).
+__device__ inline int find_item(const int* start, int n, int w)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}

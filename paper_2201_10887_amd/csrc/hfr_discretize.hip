@@ -26,6 +26,7 @@
 //     sum max(g - E, 0) and sum max(g - E, 0) v.
 // More candidates than fit in LDS are handled in rounds (rescan, next slice).
 #include <cmath>
+#include <type_traits>
 
 #include "hfr_device.h"
 
@@ -39,22 +40,9 @@ constexpr int TCAP = 128;     // tile-list records per chunk
 constexpr int UNROLL = 2;     // node-table loads in flight per lane during the scan
 constexpr float LOG2E = 1.4426950408889634f;
 
-struct Tables {
-    const float4* packed;
-    const float* radius;
-    const int32_t* node;
-    const float* sigma;
-    int n, max_depth;
-    double x0, y0, side, inv_side;
-    float E;   // exp(-cutoff^2 / 2)
-    float T2;  // (s r)^2 at the truncation radius: cutoff^2 log2(e) / 2
-};
 
 constexpr float HALF_LOG2E = 0.72134752044448170f;
 
-struct Dom2 {
-    double x0, y0, x1, y1;
-};
 
 struct Rect {
     double x0, y0, x1, y1;
@@ -288,26 +276,33 @@ __device__ inline TileFrame tile_frame(const TexCascade& C, const Dom2& D, const
     return f;
 }
 
-__global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
-                                                         float* __restrict__ tex, uint16_t* __restrict__ mask)
+struct DiscShared {
+    float4 brec[BCAP];
+    int bids[BCAP];
+    float4 trec_all[WAVES][TCAP];
+    double rxl[BS + 1], rxr[BS + 1];
+    uint32_t mbits[BS];
+    int wcnt[WAVES];
+    int any_vis;
+};
+
+// Texels of block (bx, by) of one cascade; every thread of the workgroup
+// takes part.
+__device__ __forceinline__ void discretize_block(const Tables& T, const TexCascade& C, const Dom2& D, int bx, int by,
+                                                 float* __restrict__ tex, uint16_t* __restrict__ mask, DiscShared& sh)
 {
-    __shared__ float4 brec[BCAP];
-    __shared__ int bids[BCAP];
-    __shared__ float4 trec_all[WAVES][TCAP];
-    __shared__ double rxl[BS + 1], rxr[BS + 1];
-    __shared__ uint32_t mbits[BS];
-    __shared__ int wcnt[WAVES];
-    __shared__ int any_vis;
+    float4* brec = sh.brec;
+    int* bids = sh.bids;
+    int* wcnt = sh.wcnt;
+    int& any_vis = sh.any_vis;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int bx, by;
-    block_coords(gx, gy, &bx, &by);
     const int bi0 = bx * BS, bj0 = by * BS;
     const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
     const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
     const bool inside = i < N && j < N;
     if (threadIdx.x == 0) any_vis = 0;
-    const bool vis = block_visibility(C, bi0, bj0, i, j, rxl, rxr, mbits, mask);
+    const bool vis = block_visibility(C, bi0, bj0, i, j, sh.rxl, sh.rxr, sh.mbits, mask);
     if (vis) any_vis = 1;
     __syncthreads();
     if (!any_vis) {
@@ -319,7 +314,7 @@ __global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C,
     const bool tile_vis = __ballot(vis) != 0;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const float lim = T.T2 * 1.0001f, E = T.E;
-    float4* trec = trec_all[wave];
+    float4* trec = sh.trec_all[wave];
     float s0 = 0.0f, s1 = 0.0f, vpart = 0.0f;
     int n_eval = 0;
     for (int lo = 0;; lo += BCAP) {
@@ -390,26 +385,41 @@ __global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C,
     tex[(int64_t)j * N + i] = out;
 }
 
+__global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+                                                         float* __restrict__ tex, uint16_t* __restrict__ mask)
+{
+    __shared__ DiscShared sh;
+    int bx, by;
+    block_coords(gx, gy, &bx, &by);
+    discretize_block(T, C, D, bx, by, tex, mask, sh);
+}
+
 // Adjoint of Eq. 2 / Eq. 1.  Lanes first own texels (S0 of each texel), then
 // own tile-list leaves: for every texel of the tile with a non-zero gradient
 // (a wave-uniform loop) each lane adds its leaf's share
 //   g w_j / S0   and   g (v_j - v_s) / S0 * exp(-q^2/2) q^2 / sigma_j,
 // and finally adds its two sums to the leaf's gradient with one atomic each.
-__global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
-                                                                  const float* __restrict__ tex,
-                                                                  const float* __restrict__ gtex,
-                                                                  float* __restrict__ gv, float* __restrict__ gs)
+struct DiscBwdShared {
+    float4 brec[BCAP];
+    int bids[BCAP];
+    float bsig[BCAP];
+    unsigned short tidx_all[WAVES][BCAP];
+    int wcnt[WAVES];
+    int any_act;
+};
+
+__device__ __forceinline__ void discretize_backward_block(const Tables& T, const TexCascade& C, const Dom2& D, int bx,
+                                                          int by, const float* __restrict__ tex,
+                                                          const float* __restrict__ gtex, float* __restrict__ gv,
+                                                          float* __restrict__ gs, DiscBwdShared& sh)
 {
-    __shared__ float4 brec[BCAP];
-    __shared__ int bids[BCAP];
-    __shared__ float bsig[BCAP];
-    __shared__ unsigned short tidx_all[WAVES][BCAP];
-    __shared__ int wcnt[WAVES];
-    __shared__ int any_act;
+    float4* brec = sh.brec;
+    int* bids = sh.bids;
+    float* bsig = sh.bsig;
+    int* wcnt = sh.wcnt;
+    int& any_act = sh.any_act;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int bx, by;
-    block_coords(gx, gy, &bx, &by);
     const int bi0 = bx * BS, bj0 = by * BS;
     const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
     const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
@@ -430,7 +440,7 @@ __global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexC
     const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j);
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const float lim = T.T2 * 1.0001f, E = T.E;
-    unsigned short* tidx = tidx_all[wave];
+    unsigned short* tidx = sh.tidx_all[wave];
     // pass 1: S0 per texel (lanes own texels)
     float s0 = 0.0f;
     int total = 0;
@@ -508,7 +518,66 @@ __global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexC
     }
 }
 
-hfr_status tables_of(const hfr_leaves* L, bool backward, Tables* out)
+__global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+                                                                  const float* __restrict__ tex,
+                                                                  const float* __restrict__ gtex,
+                                                                  float* __restrict__ gv, float* __restrict__ gs)
+{
+    __shared__ DiscBwdShared sh;
+    int bx, by;
+    block_coords(gx, gy, &bx, &by);
+    discretize_backward_block(T, C, D, bx, by, tex, gtex, gv, gs, sh);
+}
+
+// Persistent form over every cascade of every view of a batch: each
+// workgroup takes runs of DISC_GRAIN 16 x 16 texel blocks from the queues
+// until all are done; the cascade a block belongs to is found by one search
+// per run and followed forward inside it.
+constexpr int DISC_GRAIN = 8;
+
+template <bool BACKWARD>
+__global__ __launch_bounds__(256) void discretize_batch_kernel(BatchDev P)
+{
+    __shared__ typename std::conditional<BACKWARD, DiscBwdShared, DiscShared>::type sh;
+    __shared__ int work[3];
+    int* q = P.queues + (BACKWARD ? HFR_QUEUE_DISC_BWD : HFR_QUEUE_DISC);
+    const int total = P.tex_start[P.n_tex];
+    const int xcd = blockIdx.x & 7;
+    for (;;) {
+        __syncthreads();  // the previous run's LDS reads are done
+        if (threadIdx.x == 0) {
+            int w0 = -1, w1 = -1;
+            const bool got = queue_grab(q, total, xcd, DISC_GRAIN, &w0, &w1);
+            work[0] = got ? w0 : -1;
+            work[1] = w1;
+            work[2] = got ? find_item(P.tex_start, P.n_tex, w0) : 0;
+        }
+        __syncthreads();
+        const int w0 = __builtin_amdgcn_readfirstlane(work[0]);
+        if (w0 < 0) break;
+        const int w1 = __builtin_amdgcn_readfirstlane(work[1]);
+        int item = __builtin_amdgcn_readfirstlane(work[2]);
+        int item_lo = P.tex_start[item], item_hi = P.tex_start[item + 1];
+        for (int w = w0; w < w1; ++w) {
+            while (w >= item_hi) {  // w < total, so this stops at an item that holds w
+                ++item;
+                item_lo = item_hi;
+                item_hi = P.tex_start[item + 1];
+            }
+            const BatchTex& it = P.tex[item];
+            const BatchField& F = P.fields[it.field];
+            const int local = w - item_lo;
+            const int bx = local % it.gx, by = local / it.gx;
+            if constexpr (BACKWARD) discretize_backward_block(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs, sh);
+            else discretize_block(F.T, it.C, F.D, bx, by, it.tex, it.mask, sh);
+            __syncthreads();  // LDS is reused by the next block of the run
+        }
+    }
+}
+
+}  // namespace
+
+hfr_status leaf_tables(const hfr_leaves* L, bool backward, Tables* out)
 {
     HFR_REQUIRE(L != nullptr, "leaves are NULL");
     HFR_REQUIRE(L->n >= 1 && L->n <= INT32_MAX, "leaf count %lld outside [1, INT32_MAX]", (long long)L->n);
@@ -524,7 +593,6 @@ hfr_status tables_of(const hfr_leaves* L, bool backward, Tables* out)
     return HFR_OK;
 }
 
-}  // namespace
 
 extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
 {
@@ -550,7 +618,7 @@ extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom,
                                      float* tex, uint32_t* mask, hfr_stream stream)
 {
     Tables T;
-    hfr_status st = tables_of(L, false, &T);
+    hfr_status st = leaf_tables(L, false, &T);
     if (st == HFR_OK) st = check_cascades(cas, K);
     if (st == HFR_OK) st = check_domain(dom);
     if (st != HFR_OK) return st;
@@ -573,7 +641,7 @@ extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_dom
                                               float* grad_sigma, hfr_stream stream)
 {
     Tables T;
-    hfr_status st = tables_of(L, true, &T);
+    hfr_status st = leaf_tables(L, true, &T);
     if (st == HFR_OK) st = check_cascades(cas, K);
     if (st == HFR_OK) st = check_domain(dom);
     if (st != HFR_OK) return st;
@@ -588,4 +656,12 @@ extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_dom
         HFR_LAUNCH_CHECK("discretize_backward");
     }
     return hfr_ok();
+}
+
+hfr_status launch_discretize_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s)
+{
+    if (backward) discretize_batch_kernel<true><<<dim3(blocks), dim3(64 * WAVES), 0, s>>>(P);
+    else discretize_batch_kernel<false><<<dim3(blocks), dim3(64 * WAVES), 0, s>>>(P);
+    HFR_LAUNCH_CHECK(backward ? "discretize_backward (batch)" : "discretize (batch)");
+    return HFR_OK;
 }

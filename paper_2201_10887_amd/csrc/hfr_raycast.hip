@@ -14,18 +14,7 @@
 
 namespace {
 
-struct RayCas {
-    double near_d, far_d, split_d, ox, oy, vx, vy, x0, y0, hx, hy, inv_hx, inv_hy;
-    int n, levels;
-};
 
-struct RayArgs {
-    double o[3], fwd[3], right[3], up[3];
-    double tx, ty;
-    int W, H, K, N;
-    double X0, Y0, X1, Y1, zmax;
-    RayCas c[HFR_MAX_CASCADES];
-};
 
 struct Ray {
     double o[3], d[3], inv_d[2];
@@ -209,13 +198,15 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
     return false;
 }
 
+// Pixel (col, row) of one view.  In the adjoint every lane of the wave must
+// call it (the gradient scatter uses wave-wide shuffles), also lanes
+// outside the image.
 template <bool BACKWARD>
-__global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
-                                                      const float* __restrict__ mip, float* __restrict__ depth,
-                                                      int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                                      float* __restrict__ gtex)
+__device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row, const float* __restrict__ tex,
+                                              const float* __restrict__ mip, float* __restrict__ depth,
+                                              int32_t* __restrict__ hit, const float* __restrict__ gdepth,
+                                              float* __restrict__ gtex)
 {
-    const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
     const bool in_image = col < A.W && row < A.H;
     if (!BACKWARD && !in_image) return;
     const int64_t p = (int64_t)row * A.W + col;
@@ -317,7 +308,7 @@ __global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __
             w[3] = (float)(sc * u * v);
             key = (H.k << 26) | (H.j << 13) | H.i;
         }
-        const int lane = __lane_id();  // hardware lane: the workgroup is 2-D, threadIdx.x is only the column
+        const int lane = __lane_id();
         uint64_t pending = __ballot(has);
         for (int it = 0; it < 4 && pending; ++it) {
             const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -353,7 +344,55 @@ __global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __
     }
 }
 
-hfr_status make_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K, RayArgs* A)
+template <bool BACKWARD>
+__global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
+                                                      const float* __restrict__ mip, float* __restrict__ depth,
+                                                      int32_t* __restrict__ hit, const float* __restrict__ gdepth,
+                                                      float* __restrict__ gtex)
+{
+    raycast_pixel<BACKWARD>(A, blockIdx.x * 16 + threadIdx.x, blockIdx.y * 16 + threadIdx.y, tex, mip, depth, hit,
+                            gdepth, gtex);
+}
+
+// Persistent form over every view of a batch: each wave takes runs of
+// RAY_GRAIN 64-pixel tiles (tile_w x 64 / tile_w) from the queues until all
+// are done; waves never wait for each other.
+constexpr int RAY_GRAIN = 4;
+
+template <bool BACKWARD>
+__global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
+{
+    int* q = P.queues + (BACKWARD ? HFR_QUEUE_RAY_BWD : HFR_QUEUE_RAY);
+    const int total = P.ray_start[P.n_views];
+    const int xcd = blockIdx.x & 7;
+    const int lane = __lane_id();
+    const int tw = P.tile_w, th = 64 / tw;
+    for (;;) {
+        int w0 = -1, w1 = -1, v = 0;
+        if (lane == 0 && queue_grab(q, total, xcd, RAY_GRAIN, &w0, &w1)) v = find_item(P.ray_start, P.n_views, w0);
+        w0 = __shfl(w0, 0);
+        if (w0 < 0) break;
+        w1 = __shfl(w1, 0);
+        v = __shfl(v, 0);
+        int v_lo = P.ray_start[v], v_hi = P.ray_start[v + 1];
+        for (int w = w0; w < w1; ++w) {
+            while (w >= v_hi) {  // w < total, so this stops at a view that holds w
+                ++v;
+                v_lo = v_hi;
+                v_hi = P.ray_start[v + 1];
+            }
+            const BatchView& V = P.views[v];
+            const int local = w - v_lo;
+            const int tx = local % V.tiles_x, ty = local / V.tiles_x;
+            raycast_pixel<BACKWARD>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,
+                                    V.gdepth, V.gtex);
+        }
+    }
+}
+
+}  // namespace
+
+hfr_status ray_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K, RayArgs* A)
 {
     HFR_REQUIRE(cam != nullptr, "camera is NULL");
     hfr_status st = check_cascades(cas, K);
@@ -394,13 +433,12 @@ hfr_status make_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_cas
     return HFR_OK;
 }
 
-}  // namespace
 
 extern "C" hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
                                   const float* tex, const float* mip, float* depth, int32_t* hit, hfr_stream stream)
 {
     RayArgs A;
-    hfr_status st = make_args(cam, dom, cas, K, &A);
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
     const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
@@ -414,7 +452,7 @@ extern "C" hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_doma
                                            float* grad_tex, hfr_stream stream)
 {
     RayArgs A;
-    hfr_status st = make_args(cam, dom, cas, K, &A);
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && grad_depth && grad_tex, "NULL texture, mipmap or gradient");
     const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
@@ -422,4 +460,12 @@ extern "C" hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_doma
                                                                          grad_tex);
     HFR_LAUNCH_CHECK("raycast_backward");
     return hfr_ok();
+}
+
+hfr_status launch_raycast_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s)
+{
+    if (backward) raycast_batch_kernel<true><<<dim3(blocks), dim3(256), 0, s>>>(P);
+    else raycast_batch_kernel<false><<<dim3(blocks), dim3(256), 0, s>>>(P);
+    HFR_LAUNCH_CHECK(backward ? "raycast_backward (batch)" : "raycast (batch)");
+    return HFR_OK;
 }

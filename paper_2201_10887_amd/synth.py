@@ -214,3 +214,62 @@ def resample_raster(dem: np.ndarray, side: float, x0: float, y0: float, hx: floa
     gx = np.clip(np.floor((x0 + np.arange(n) * hx) / side * m).astype(np.int64), 0, m - 1)
     gy = np.clip(np.floor((y0 + np.arange(n) * hy) / side * m).astype(np.int64), 0, m - 1)
     return dem[np.ix_(gy, gx)].astype(np.float32)
+
+
+# ------------------------------------------------------------------ batched workload
+#
+# Many views of several heightfields of uneven size: 8 fields whose leaf
+# counts are drawn log-uniformly between 10k and 4M (depth 8 to 12, finest
+# cell 10 m, side 10 m * 2^depth), and 64 cameras, camera c viewing field
+# c mod 8 with a resolution drawn from {256^2, 512^2, 1280x720, 1920x1080},
+# K drawn from {2, 3, 4}, and a pose as ``random_cameras`` draws it.
+
+BATCH_RESOLUTIONS = [(256, 256), (512, 512), (1280, 720), (1920, 1080)]
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchFieldSpec:
+    depth: int
+    side: float
+    dem_n: int
+    octaves: int
+    seed: int
+    target_leaves: int
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchViewSpec:
+    field: int
+    width: int
+    height: int
+    K: int
+
+
+def batch_fields(n_fields: int = 8, seed: int = 1004, lo: float = 1e4, hi: float = 4e6) -> List[BatchFieldSpec]:
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(n_fields):
+        target = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        depth = int(min(12, max(8, math.ceil(math.log(target, 4)) + 1)))
+        n = 2 ** depth
+        out.append(BatchFieldSpec(depth=depth, side=10.0 * n, dem_n=n, octaves=depth, seed=seed + 1 + f,
+                                  target_leaves=target))
+    return out
+
+
+def batch_views(n_views: int = 64, n_fields: int = 8, seed: int = 1004) -> List[BatchViewSpec]:
+    rng = np.random.default_rng(seed + 100)
+    out = []
+    for c in range(n_views):
+        w, h = BATCH_RESOLUTIONS[rng.integers(len(BATCH_RESOLUTIONS))]
+        out.append(BatchViewSpec(field=c % n_fields, width=w, height=h, K=int(rng.integers(2, 5))))
+    return out
+
+
+def batch_cameras(dems: List[np.ndarray], fields: List[BatchFieldSpec], views: List[BatchViewSpec],
+                  seed: int = 1004) -> List[Camera]:
+    out = []
+    for c, v in enumerate(views):
+        f = fields[v.field]
+        out.append(random_cameras(dems[v.field], f.side, 1, seed + 1000 + c, [(v.width, v.height)])[0])
+    return out

@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 2
+    assert api.abi_version() == 3
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -196,4 +196,41 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 2
+    assert lib.hfr_abi_version() == 3
+
+
+def test_batch_arguments_rejected_before_any_device_call():
+    """Every check of hfr_batch_plan_create runs on the host before the plan touches HIP."""
+    lib = _lib.load()
+    dummy = 0x1000
+    dom = api.domain(synth.Domain(0, 0, 100, 100, 0, 10))
+    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 3.5, 0.0, 0.0, 100.0)
+    fields = (_lib.BatchField * 1)()
+    fields[0].leaves, fields[0].dom = L, dom
+
+    def view(**kw):
+        v = _lib.BatchView(0, 2, 64, 32, 24, 0.5, 0.05, 1.0, dummy, None, dummy, dummy, dummy, None, None)
+        for k, x in kw.items():
+            setattr(v, k, x)
+        return (_lib.BatchView * 1)(v)
+
+    h = ctypes.c_void_p()
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(), 0, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 0, view(), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(field=1), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(N=48), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(K=9), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(width=0), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(tex=None), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(c_min=0.0), 1, ctypes.byref(h))
+    _raise_einval("hfr_batch_plan_create", fields, 1, view(split_lambda=1.5), 1, ctypes.byref(h))
+    bad = (_lib.BatchField * 1)()
+    bad[0].leaves, bad[0].dom = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, 4, 3.5,
+                                           0.0, 0.0, 100.0), dom
+    _raise_einval("hfr_batch_plan_create", bad, 1, view(), 1, ctypes.byref(h))
+    assert h.value is None
+    t = _lib.BatchTuning(4, 4, 12)
+    _raise_einval("hfr_batch_set_tuning", None, ctypes.byref(t))
+    _raise_einval("hfr_batch_launch", None, None)
+    _raise_einval("hfr_batch_launch_backward", None, None)
+    _raise_einval("hfr_batch_cascades", None, 0, (api.Cascade * 1)())
