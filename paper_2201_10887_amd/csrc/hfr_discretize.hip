@@ -161,71 +161,125 @@ __device__ inline bool block_visibility(const TexCascade& C, int bi0, int bj0, i
     return vis;
 }
 
-// Cooperative block scan: every leaf whose centre is closer than its level's
-// radius to the block rectangle, in the fixed order (level, element, wave,
-// lane); indices with rank in [lo, lo + BCAP) go to bids.  Returns the total
-// count (block-uniform).  Every wave of the block must call it.
-__device__ int block_scan(const Tables& T, const Rect& r, int lo, int* bids, int* wcnt, int wave, int lane)
+// Lattice window of one quadtree level around a block rectangle.
+struct LevelWin {
+    double c, R2;  // cell size, squared truncation radius
+    int64_t off;   // offset of the level in the node table
+    int start;     // first element of this level in the flattened (level, element) order
+    int ia, ja, wi, S;
+    float inv_w;
+};
+constexpr int MAX_LEVELS = 16;
+
+struct ScanShared {
+    LevelWin lw[MAX_LEVELS];
+    int start[MAX_LEVELS + 1];
+    int wcnt[WAVES];
+};
+
+// Windows of every level around the block rectangle (thread l fills level l),
+// flattened into one element range: level l owns [start[l], start[l + 1]).
+// Returns the total element count (block-uniform).
+__device__ int block_levels(const Tables& T, const Rect& r, ScanShared& sc)
+{
+    const int t = threadIdx.x;
+    if (t <= T.max_depth) {
+        const int l = t;
+        LevelWin w{};
+        int cnt = 0;
+        const float Rf = T.radius[l];
+        if (Rf > 0.0f) {
+            const double R = Rf;
+            const double c = ldexp(T.side, -l), inv_c = ldexp(T.inv_side, l);
+            const int S = 1 << l;
+            const int ia = max(0, (int)floor((r.x0 - R - T.x0) * inv_c - 0.5) - 1);
+            const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) * inv_c - 0.5) + 1);
+            const int ja = max(0, (int)floor((r.y0 - R - T.y0) * inv_c - 0.5) - 1);
+            const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) * inv_c - 0.5) + 1);
+            const int wi = ib - ia + 1, hj = jb - ja + 1;
+            if (wi > 0 && hj > 0) {
+                cnt = wi * hj;
+                w = LevelWin{c, R * R, ((int64_t(1) << (2 * l)) - 1) / 3, 0, ia, ja, wi, S, 1.0f / (float)wi};
+            }
+        }
+        sc.lw[l] = w;
+        sc.start[l + 1] = cnt;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int l = 0; l <= T.max_depth; ++l) {
+            const int cnt = sc.start[l + 1];
+            sc.start[l] = acc;
+            sc.lw[l].start = acc;
+            acc += cnt;
+        }
+        for (int l = T.max_depth + 1; l <= MAX_LEVELS; ++l) sc.start[l] = acc;
+    }
+    __syncthreads();
+    return sc.start[MAX_LEVELS];
+}
+
+// Cooperative block scan over the flattened windows: every leaf whose centre
+// is closer than its level's radius to the block rectangle, in the fixed
+// order (level, element); indices with rank in [lo, lo + BCAP) go to bids.
+// Returns the total count (block-uniform).  Every wave of the block must call
+// it, after block_levels.
+__device__ int block_scan(const Tables& T, const Rect& r, int n_el, int lo, int* bids, ScanShared& sc, int wave,
+                          int lane)
 {
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     int total = 0;
-    for (int l = 0; l <= T.max_depth; ++l) {
-        const float Rf = T.radius[l];
-        if (!(Rf > 0.0f)) continue;
-        const double R = Rf;
-        const double c = ldexp(T.side, -l), inv_c = ldexp(T.inv_side, l);
-        const int S = 1 << l;
-        const int ia = max(0, (int)floor((r.x0 - R - T.x0) * inv_c - 0.5) - 1);
-        const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) * inv_c - 0.5) + 1);
-        const int ja = max(0, (int)floor((r.y0 - R - T.y0) * inv_c - 0.5) - 1);
-        const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) * inv_c - 0.5) + 1);
-        const int wi = ib - ia + 1, hj = jb - ja + 1;
-        if (wi <= 0 || hj <= 0) continue;
-        const int cnt = __builtin_amdgcn_readfirstlane(wi * hj);
-        const float inv_w = 1.0f / (float)wi;
-        const int32_t* lvl = T.node + ((int64_t(1) << (2 * l)) - 1) / 3;
-        const double R2 = R * R;
-        for (int e0 = 0; e0 < cnt; e0 += 256 * UNROLL) {
-            int id[UNROLL], ii[UNROLL], jj[UNROLL];
+    for (int e0 = 0; e0 < n_el; e0 += 256 * UNROLL) {
+        int id[UNROLL], ii[UNROLL], jj[UNROLL], lv[UNROLL];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int e = e0 + u * 256 + (int)threadIdx.x;
-                id[u] = -1;
-                ii[u] = jj[u] = 0;
-                if (e < cnt) {
-                    int q = (int)((float)e * inv_w);
-                    int rem = e - q * wi;
-                    if (rem < 0) { --q; rem += wi; }
-                    if (rem >= wi) { ++q; rem -= wi; }
-                    ii[u] = ia + rem;
-                    jj[u] = ja + q;
-                    id[u] = lvl[(int64_t)jj[u] * S + ii[u]];
-                }
+        for (int u = 0; u < UNROLL; ++u) {
+            const int e = e0 + u * 256 + (int)threadIdx.x;
+            id[u] = -1;
+            ii[u] = jj[u] = lv[u] = 0;
+            if (e < n_el) {
+                // the level owning e: the largest l with start[l] <= e (empty levels share
+                // their successor's start, so the largest such l owns elements)
+                int l = 0;
+#pragma unroll
+                for (int step = MAX_LEVELS / 2; step > 0; step >>= 1)
+                    if (sc.start[l + step] <= e) l += step;
+                const LevelWin& w = sc.lw[l];
+                const int local = e - w.start;
+                int q = (int)((float)local * w.inv_w);
+                int rem = local - q * w.wi;
+                if (rem < 0) { --q; rem += w.wi; }
+                if (rem >= w.wi) { ++q; rem -= w.wi; }
+                ii[u] = w.ia + rem;
+                jj[u] = w.ja + q;
+                lv[u] = l;
+                id[u] = T.node[w.off + (int64_t)jj[u] * w.S + ii[u]];
             }
+        }
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                int v = id[u];
-                if (v >= 0) {
-                    const double cx = T.x0 + (ii[u] + 0.5) * c, cy = T.y0 + (jj[u] + 0.5) * c;
-                    const double dx = fmax(fmax(r.x0 - cx, cx - r.x1), 0.0);
-                    const double dy = fmax(fmax(r.y0 - cy, cy - r.y1), 0.0);
-                    if (!(dx * dx + dy * dy < R2) || v >= T.n) v = -1;
-                }
-                const uint64_t m = __ballot(v >= 0);
-                if (lane == 0) wcnt[wave] = __popcll(m);
-                __syncthreads();
-                int base = total, all = 0;
-#pragma unroll
-                for (int w = 0; w < WAVES; ++w) {
-                    const int k = wcnt[w];
-                    base += w < wave ? k : 0;
-                    all += k;
-                }
-                const int slot = base + __popcll(m & lt) - lo;
-                if (v >= 0 && slot >= 0 && slot < BCAP) bids[slot] = v;
-                total += all;
-                __syncthreads();
+        for (int u = 0; u < UNROLL; ++u) {
+            int v = id[u];
+            if (v >= 0) {
+                const LevelWin& w = sc.lw[lv[u]];
+                const double cx = T.x0 + (ii[u] + 0.5) * w.c, cy = T.y0 + (jj[u] + 0.5) * w.c;
+                const double dx = fmax(fmax(r.x0 - cx, cx - r.x1), 0.0);
+                const double dy = fmax(fmax(r.y0 - cy, cy - r.y1), 0.0);
+                if (!(dx * dx + dy * dy < w.R2) || v >= T.n) v = -1;
             }
+            const uint64_t m = __ballot(v >= 0);
+            if (lane == 0) sc.wcnt[wave] = __popcll(m);
+            __syncthreads();
+            int base = total, all = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const int k = sc.wcnt[w];
+                base += w < wave ? k : 0;
+                all += k;
+            }
+            const int slot = base + __popcll(m & lt) - lo;
+            if (v >= 0 && slot >= 0 && slot < BCAP) bids[slot] = v;
+            total += all;
+            __syncthreads();
         }
     }
     return total;
@@ -282,7 +336,7 @@ struct DiscShared {
     float4 trec_all[WAVES][TCAP];
     double rxl[BS + 1], rxr[BS + 1];
     uint32_t mbits[BS];
-    int wcnt[WAVES];
+    ScanShared scan;
     int any_vis;
 };
 
@@ -293,7 +347,6 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
 {
     float4* brec = sh.brec;
     int* bids = sh.bids;
-    int* wcnt = sh.wcnt;
     int& any_vis = sh.any_vis;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -317,8 +370,9 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     float4* trec = sh.trec_all[wave];
     float s0 = 0.0f, s1 = 0.0f, vpart = 0.0f;
     int n_eval = 0;
+    const int n_el = block_levels(T, br, sh.scan);
     for (int lo = 0;; lo += BCAP) {
-        const int total = block_scan(T, br, lo, bids, wcnt, wave, lane);
+        const int total = block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
         const int nb = min(total - lo, BCAP);
         stage_block(T, br, bids, nb, brec, nullptr);
         __syncthreads();
@@ -404,7 +458,7 @@ struct DiscBwdShared {
     int bids[BCAP];
     float bsig[BCAP];
     unsigned short tidx_all[WAVES][BCAP];
-    int wcnt[WAVES];
+    ScanShared scan;
     int any_act;
 };
 
@@ -416,7 +470,6 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     float4* brec = sh.brec;
     int* bids = sh.bids;
     float* bsig = sh.bsig;
-    int* wcnt = sh.wcnt;
     int& any_act = sh.any_act;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -444,8 +497,9 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     // pass 1: S0 per texel (lanes own texels)
     float s0 = 0.0f;
     int total = 0;
+    const int n_el = block_levels(T, br, sh.scan);
     for (int lo = 0;; lo += BCAP) {
-        total = block_scan(T, br, lo, bids, wcnt, wave, lane);
+        total = block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
         const int nb = min(total - lo, BCAP);
         stage_block(T, br, bids, nb, brec, bsig);
         __syncthreads();
@@ -473,7 +527,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
         const int nb = min(total - lo, BCAP);
         if (total > BCAP) {
             __syncthreads();
-            block_scan(T, br, lo, bids, wcnt, wave, lane);
+            block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
             stage_block(T, br, bids, nb, brec, bsig);
             __syncthreads();
         }

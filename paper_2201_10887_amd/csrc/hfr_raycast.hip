@@ -370,10 +370,12 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
     for (;;) {
         int w0 = -1, w1 = -1, v = 0;
         if (lane == 0 && queue_grab(q, total, xcd, RAY_GRAIN, &w0, &w1)) v = find_item(P.ray_start, P.n_views, w0);
-        w0 = __shfl(w0, 0);
+        // every lane is active here, so the first active lane is lane 0: the
+        // values become wave-uniform (scalar registers, scalar descriptor loads)
+        w0 = __builtin_amdgcn_readfirstlane(w0);
         if (w0 < 0) break;
-        w1 = __shfl(w1, 0);
-        v = __shfl(v, 0);
+        w1 = __builtin_amdgcn_readfirstlane(w1);
+        v = __builtin_amdgcn_readfirstlane(v);
         int v_lo = P.ray_start[v], v_hi = P.ray_start[v + 1];
         for (int w = w0; w < w1; ++w) {
             while (w >= v_hi) {  // w < total, so this stops at a view that holds w

@@ -75,11 +75,17 @@ def test_autograd_equals_adjoint_entry_points(gpu, problem, gpu_grads):
 
 
 def test_loss_gradient_matches_oracle(problem, gpu_grads):
+    """Each side differentiates its own forward pass (textures equal within the texel
+    tolerance, depths within the depth tolerance), so the loss gradient per pixel differs
+    by up to twice the depth difference: the norm-relative bound holds, and every leaf's
+    difference is bounded by 1e-3 of the largest gradient (a leaf whose own gradient is
+    small can differ by more than 1e-3 of itself)."""
     assert abs(gpu_grads["loss"] - problem["loss0"]) <= 1e-3 * problem["loss0"]
     for got, want in ((gpu_grads["gv"], problem["gv"]), (gpu_grads["gs"], problem["gs"])):
-        err, per = G.grad_close(got, want)
+        err, _ = G.grad_close(got, want)
         assert err <= 1e-3, err
-        assert per.mean() >= 0.98, per.mean()
+        worst = np.abs(got - want).max() / np.abs(want).max()
+        assert worst <= 1e-3, worst
 
 
 @pytest.mark.parametrize("which", ["v", "sigma"])
