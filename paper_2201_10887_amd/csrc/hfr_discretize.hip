@@ -439,7 +439,9 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     tex[(int64_t)j * N + i] = out;
 }
 
-__global__ __launch_bounds__(256) void discretize_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+// 8 waves per SIMD (64 VGPRs, no spills; 8 blocks of LDS fit a CU): the near
+// cascades wait on node-table and record loads, and more resident waves hide that.
+__global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
                                                          float* __restrict__ tex, uint16_t* __restrict__ mask)
 {
     __shared__ DiscShared sh;
@@ -572,7 +574,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     }
 }
 
-__global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+__global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
                                                                   const float* __restrict__ tex,
                                                                   const float* __restrict__ gtex,
                                                                   float* __restrict__ gv, float* __restrict__ gs)
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(256) void discretize_backward_kernel(Tables T, TexC
 constexpr int DISC_GRAIN = 8;
 
 template <bool BACKWARD>
-__global__ __launch_bounds__(256) void discretize_batch_kernel(BatchDev P)
+__global__ __launch_bounds__(256, BACKWARD ? 5 : 6) void discretize_batch_kernel(BatchDev P)
 {
     __shared__ typename std::conditional<BACKWARD, DiscBwdShared, DiscShared>::type sh;
     __shared__ int work[3];
