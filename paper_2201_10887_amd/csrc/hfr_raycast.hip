@@ -25,10 +25,13 @@ struct Hit {
     double t, u, v, fp;
 };
 
-__device__ inline int64_t level_offset(int N, int l)
+// Offset of level l in a max-mipmap of N = 2^L texels per side: the sizes of
+// the finer levels, 4^L + ... + 4^(L-l+1) = P(L+1) - P(L-l+1) with P(n) =
+// (4^n - 1) / 3, the base-4 repunit 0x55...5 of n digits.  For N <= 8192 it
+// fits in 32 bits.
+__device__ inline int level_offset(int L, int l)
 {
-    const int64_t n = N, s = N >> l;
-    return (4 * n * n - 4 * s * s) / 3;
+    return (int)((0x55555555u >> (30 - 2 * L)) - (0x55555555u >> (30 - 2 * (L - l))));
 }
 
 __device__ inline void slab(double o, double d, double lo, double hi, double& t0, double& t1)
@@ -128,12 +131,14 @@ __device__ inline bool smallest_root(double a, double b, double c, double tau1, 
 // Node of level l holding cell (ci, cj): exit parameter along the ray.
 __device__ inline double node_exit(const Ray& r, const RayCas& c, int ci, int cj, int l, double tb)
 {
+    // the boundary the ray leaves through on each axis: (I + 1) << l moving up, I << l moving down
+    const int bx = ((ci >> l) + (r.d[0] > 0.0 ? 1 : 0)) << l;
+    const int by = ((cj >> l) + (r.d[1] > 0.0 ? 1 : 0)) << l;
+    const double tx = (lattice_pos(c.x0, bx, c.hx) - r.o[0]) * r.inv_d[0];
+    const double ty = (lattice_pos(c.y0, by, c.hy) - r.o[1]) * r.inv_d[1];
     double te = tb;
-    const int I = ci >> l, J = cj >> l;
-    if (r.d[0] > 0.0) te = fmin(te, (lattice_pos(c.x0, (I + 1) << l, c.hx) - r.o[0]) * r.inv_d[0]);
-    else if (r.d[0] < 0.0) te = fmin(te, (lattice_pos(c.x0, I << l, c.hx) - r.o[0]) * r.inv_d[0]);
-    if (r.d[1] > 0.0) te = fmin(te, (lattice_pos(c.y0, (J + 1) << l, c.hy) - r.o[1]) * r.inv_d[1]);
-    else if (r.d[1] < 0.0) te = fmin(te, (lattice_pos(c.y0, J << l, c.hy) - r.o[1]) * r.inv_d[1]);
+    if (r.d[0] != 0.0) te = fmin(te, tx);
+    if (r.d[1] != 0.0) te = fmin(te, ty);
     return te;
 }
 
@@ -151,7 +156,7 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
     const int max_iter = 8 * N * (L + 2) + 64;
     for (int it = 0; it < max_iter; ++it) {
         const int S = N >> l;
-        const float M = mip[level_offset(N, l) + (int64_t)(cj >> l) * S + (ci >> l)];
+        const float M = mip[level_offset(L, l) + (cj >> l) * S + (ci >> l)];
         const double te = fmax(node_exit(r, c, ci, cj, l, tb), t1);
         const double za = r.o[2] + t * r.d[2], zb = r.o[2] + te * r.d[2];
         bool advance = false;
