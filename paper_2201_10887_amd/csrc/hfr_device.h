@@ -69,6 +69,21 @@ __device__ inline void strip_extent(const TexCascade& c, double ya, double yb, d
     *xr = hi;
 }
 
+// Tile (bx, by) of workgroup b of a 1-D grid over gx x gy tiles.  The hardware
+// deals consecutive workgroups round-robin to the 8 XCDs; remapping gives each
+// XCD one contiguous run of tiles (row-major), so neighbouring tiles, which
+// read neighbouring data, share an L2.
+__device__ inline void xcd_tile(int b, int gx, int gy, int* bx, int* by)
+{
+    const int nb = gx * gy;
+    const int per = (nb + 7) / 8;
+    const int xcd = b & 7, slot = b >> 3;
+    const int full = nb - 8 * (per - 1);  // XCDs that receive `per` tiles (the rest get per - 1)
+    const int lin = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
+    *bx = lin % gx;
+    *by = lin / gx;
+}
+
 // Validates the common texture arguments of a set of cascades.
 inline hfr_status check_cascades(const hfr_cascade* cas, int32_t K)
 {

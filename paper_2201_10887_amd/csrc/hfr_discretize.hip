@@ -94,22 +94,6 @@ __device__ inline Rect texel_rect(const TexCascade& C, const Dom2& D, int i0, in
     return r;
 }
 
-// Block (bx, by) of this workgroup.  The hardware deals consecutive
-// workgroups round-robin to the 8 XCDs; remapping gives each XCD one
-// contiguous run of blocks, so neighbouring blocks (which read the same
-// node-table rows and leaf records) share an L2.
-__device__ inline void block_coords(int gx, int gy, int* bx, int* by)
-{
-    const int nb = gx * gy;
-    const int b = blockIdx.x;
-    const int per = (nb + 7) / 8;
-    const int xcd = b & 7, slot = b >> 3;
-    const int full = nb - 8 * (per - 1);  // XCDs that receive `per` blocks (the rest get per - 1)
-    const int lin = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
-    *bx = lin % gx;
-    *by = lin / gx;
-}
-
 __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -446,7 +430,7 @@ __global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, TexCascade
 {
     __shared__ DiscShared sh;
     int bx, by;
-    block_coords(gx, gy, &bx, &by);
+    xcd_tile(blockIdx.x, gx, gy, &bx, &by);
     discretize_block(T, C, D, bx, by, tex, mask, sh);
 }
 
@@ -581,7 +565,7 @@ __global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, T
 {
     __shared__ DiscBwdShared sh;
     int bx, by;
-    block_coords(gx, gy, &bx, &by);
+    xcd_tile(blockIdx.x, gx, gy, &bx, &by);
     discretize_backward_block(T, C, D, bx, by, tex, gtex, gv, gs, sh);
 }
 

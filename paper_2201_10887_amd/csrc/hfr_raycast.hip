@@ -8,8 +8,10 @@
 // Inside a cascade the ray descends the maximum mipmap: a node is skipped
 // when the ray's lowest z over its part of the node is above the node's
 // maximum; a level-0 cell whose four texels are visible is intersected
-// with the bilinear patch in closed form.  After a skip the walk climbs to
-// the highest level whose node the ray has newly entered.
+// with the bilinear patch in closed form (its four texels also give the
+// level-0 maximum, so level 0 reads no pyramid).  After each step the walk
+// climbs at most one level; the frame time is set by the longest rays, which
+// graze the surface and gain nothing from jumping to high levels.
 #include "hfr_device.h"
 
 namespace {
@@ -155,8 +157,21 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
     // every iteration either descends a level or moves to a later piece
     const int max_iter = 8 * N * (L + 2) + 64;
     for (int it = 0; it < max_iter; ++it) {
-        const int S = N >> l;
-        const float M = mip[level_offset(L, l) + (cj >> l) * S + (ci >> l)];
+        // Node maximum: from the max-mipmap above level 0; at level 0 from the cell's own four
+        // texels (the same value the pyramid holds there), which the patch test needs anyway,
+        // so a cell costs one round of loads instead of two.
+        float M, t00 = 0.f, t10 = 0.f, t01 = 0.f, t11 = 0.f;
+        if (l > 0) {
+            M = mip[level_offset(L, l) + (cj >> l) * (N >> l) + (ci >> l)];
+        } else {
+            const int64_t b = (int64_t)cj * N + ci;
+            t00 = tex[b];
+            t10 = tex[b + 1];
+            t01 = tex[b + N];
+            t11 = tex[b + N + 1];
+            M = (isfinite(t00) && isfinite(t10) && isfinite(t01) && isfinite(t11))
+                    ? fmaxf(fmaxf(t00, t10), fmaxf(t01, t11)) : -INFINITY;
+        }
         const double te = fmax(node_exit(r, c, ci, cj, l, tb), t1);
         const double za = r.o[2] + t * r.d[2], zb = r.o[2] + te * r.d[2];
         bool advance = false;
@@ -165,8 +180,7 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
         } else if (l > 0) {
             --l;
         } else {
-            const double h00 = tex[(int64_t)cj * N + ci], h10 = tex[(int64_t)cj * N + ci + 1];
-            const double h01 = tex[(int64_t)(cj + 1) * N + ci], h11 = tex[(int64_t)(cj + 1) * N + ci + 1];
+            const double h00 = t00, h10 = t10, h01 = t01, h11 = t11;
             const double u0 = ((r.o[0] + t * r.d[0]) - c.x0) * c.inv_hx - ci;
             const double v0 = ((r.o[1] + t * r.d[1]) - c.y0) * c.inv_hy - cj;
             const double du = r.d[0] * c.inv_hx, dv = r.d[1] * c.inv_hy;
@@ -197,7 +211,10 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
             const unsigned diff = (unsigned)((ni ^ ci) | (nj ^ cj));
             ci = ni;
             cj = nj;
-            if (diff) l = min(31 - __clz(diff), L);
+            // climb at most one level per step: a node of the next level up is tried
+            // before larger ones, so a ray running close to the surface does not pay for
+            // descending from high levels at every cell
+            if (diff) l = min(31 - __clz(diff), l + 1);
         }
     }
     return false;
@@ -246,11 +263,20 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
     Hit HA, HB;
     HB.k = -1;
     bool found = false;
-    if (live && tin < tout) {
-        const double dd = r.d[0] * A.c[0].vx + r.d[1] * A.c[0].vy;
-        const bool fwd = dd >= 0.0;
-        for (int s = 0; s < A.K && !found; ++s) {
-            const int k = fwd ? s : A.K - 1 - s;
+    const double dd = r.d[0] * A.c[0].vx + r.d[1] * A.c[0].vy;
+    const bool fwd = dd >= 0.0;
+    // Cascades in the order the ray's offset sweeps them: increasing k when the offset
+    // grows along the ray, decreasing otherwise.  The two sweep directions run as two
+    // passes so that the cascade index is the same on every lane of a pass (the cascade
+    // constants then stay in scalar registers); a lane takes part in the pass of its
+    // direction and stops at its first hit.
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool up = pass == 0;
+        const bool mine = live && tin < tout && fwd == up;
+        if (__ballot(mine) == 0) continue;
+        for (int s = 0; s < A.K; ++s) {
+            if (!mine || found) continue;
+            const int k = up ? s : A.K - 1 - s;
             const RayCas& ck = A.c[k];
             double ta, tb;
             segment(r, ck, ck.near_d, ck.far_d, tin, tout, ta, tb);
@@ -260,12 +286,12 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
             hid = (HA.k << 26) | (HA.j << 13) | HA.i;
             out_t = HA.t;
             cA = 1.0;
-            const int pk = fwd ? k + 1 : k - 1;
+            const int pk = up ? k + 1 : k - 1;
             if (pk >= 0 && pk < A.K) {
-                const RayCas& cov = A.c[fwd ? k : pk];
+                const RayCas& cov = A.c[up ? k : pk];
                 const double lo = cov.split_d, hi = cov.far_d;
                 const double dA = offset_at(r, ck, HA.t);
-                if (fwd ? dA >= lo : dA <= hi) {
+                if (up ? dA >= lo : dA <= hi) {
                     double tb0, tb1;
                     segment(r, A.c[pk], lo, hi, tin, tout, tb0, tb1);
                     if (first_hit(r, A.c[pk], pk, tex + pk * NN, mip + pk * MM, tb0, tb1, HB)) {
@@ -273,7 +299,7 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
                         double al = (dA - lo) / delta, dal = dd / delta;
                         if (al <= 0.0) { al = 0.0; dal = 0.0; }
                         if (al >= 1.0) { al = 1.0; dal = 0.0; }
-                        if (fwd) {
+                        if (up) {
                             out_t = (1.0 - al) * HA.t + al * HB.t;
                             cA = (1.0 - al) + (HB.t - HA.t) * dal;
                             cB = al;
