@@ -110,6 +110,15 @@ __device__ inline void cell_at(const Ray& r, const RayCas& c, double t, int& i, 
 // Smallest tau in [0, tau1] with a tau^2 + b tau + c <= 0, given c > 0.
 __device__ inline bool smallest_root(double a, double b, double c, double tau1, double& tau)
 {
+    // Division-free rejection first (most cells a grazing ray tests hold no root).  With
+    // f(0) = c > 0 a root in [0, tau1] needs f(tau1) <= 0, or, for a convex f (a > 0), a
+    // minimum inside the interval with a non-negative discriminant.  The margins are far
+    // above FP64 rounding, so every case near the boundary takes the exact path below.
+    const double f1 = (a * tau1 + b) * tau1 + c;
+    if (f1 > 1e-12 * ((fabs(a) * tau1 + fabs(b)) * tau1 + fabs(c))) {
+        if (!(a > 0.0 && b < 0.0 && -b < 2.0 * a * tau1)) return false;
+        if (b * b - 4.0 * a * c < -1e-12 * (b * b + 4.0 * fabs(a * c))) return false;
+    }
     double best = INFINITY;
     if (a == 0.0) {
         if (b < 0.0) {
