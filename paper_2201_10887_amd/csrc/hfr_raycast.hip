@@ -10,8 +10,9 @@
 // maximum; a level-0 cell whose four texels are visible is intersected
 // with the bilinear patch in closed form (its four texels also give the
 // level-0 maximum, so level 0 reads no pyramid).  After each step the walk
-// climbs at most one level; the frame time is set by the longest rays, which
-// graze the surface and gain nothing from jumping to high levels.
+// climbs at most one level, and not at all after a cell whose patch it had to
+// test: the frame time is set by the longest rays, which graze the surface
+// and gain nothing from larger nodes.
 #include "hfr_device.h"
 
 namespace {
@@ -183,7 +184,7 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
         }
         const double te = fmax(node_exit(r, c, ci, cj, l, tb), t1);
         const double za = r.o[2] + t * r.d[2], zb = r.o[2] + te * r.d[2];
-        bool advance = false;
+        bool advance = false, close = false;
         if (fmin(za, zb) > (double)M) {
             advance = true;
         } else if (l > 0) {
@@ -210,6 +211,7 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
                 return true;
             }
             advance = true;
+            close = true;  // the ray passed below this cell's highest texel
         }
         if (advance) {
             if (te >= tb) return false;
@@ -220,10 +222,10 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
             const unsigned diff = (unsigned)((ni ^ ci) | (nj ^ cj));
             ci = ni;
             cj = nj;
-            // climb at most one level per step: a node of the next level up is tried
-            // before larger ones, so a ray running close to the surface does not pay for
-            // descending from high levels at every cell
-            if (diff) l = min(31 - __clz(diff), l + 1);
+            // climb at most one level per step, and none after a cell the ray passed below
+            // the top of: a ray running close to the surface stays on level 0 instead of
+            // testing (and descending from) a larger node at every cell
+            if (diff) l = min(31 - __clz(diff), l + (close ? 0 : 1));
         }
     }
     return false;
