@@ -335,11 +335,14 @@ typedef struct {
  * workgroups (256 threads) per compute unit for the discretize kernels and
  * the ray-cast kernels, in [1, 16].  ray_tile_w: width of the 64-pixel tile
  * a wave takes at a time (8, 16, 32 or 64; height 64 / ray_tile_w).
- * Defaults: 4, 4, 8. */
+ * disc_grain: 16 x 16 texel blocks a discretize workgroup takes per queue
+ * access, in [1, 64] (small runs keep the blocks running at once close
+ * together, large runs need fewer atomics).  Defaults: 4, 4, 32, 8. */
 typedef struct {
     int32_t disc_blocks_per_cu;
     int32_t ray_blocks_per_cu;
     int32_t ray_tile_w;
+    int32_t disc_grain;
 } hfr_batch_tuning;
 
 /* Validates the fields and views, copies their descriptors to device memory

@@ -22,8 +22,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "_build", "autotune.json")
 
 DEFAULT_GRID = {
-    "disc_blocks_per_cu": (2, 4, 8),
-    "ray_blocks_per_cu": (2, 3, 4),
+    "disc_blocks_per_cu": (4, 7),
+    "disc_grain": (4, 8, 16),
+    "ray_blocks_per_cu": (2, 4),
     "ray_tile_w": (8, 16, 32),
 }
 

@@ -69,6 +69,7 @@ hfr_status check_tuning(const hfr_batch_tuning& t)
                 t.ray_blocks_per_cu);
     HFR_REQUIRE(t.ray_tile_w == 8 || t.ray_tile_w == 16 || t.ray_tile_w == 32 || t.ray_tile_w == 64,
                 "ray_tile_w %d is not 8, 16, 32 or 64", t.ray_tile_w);
+    HFR_REQUIRE(t.disc_grain >= 1 && t.disc_grain <= 64, "disc_grain %d outside [1, 64]", t.disc_grain);
     return HFR_OK;
 }
 
@@ -84,7 +85,7 @@ struct hfr_batch_plan {
     std::vector<hfr_cascade> cas;   // from the last hfr_batch_set_cameras
     std::vector<int> tex_start, mip_start, ray_start;
     int pass_blocks[HFR_MIP_PASSES] = {0, 0, 0};
-    hfr_batch_tuning tuning{4, 4, 8};
+    hfr_batch_tuning tuning{4, 4, 32, 8};
     bool cameras_set = false, backward_ok = false, upload_pending = false;
     // pinned staging of the per-camera descriptors
     BatchTex* tex_h = nullptr;
@@ -276,7 +277,7 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
         return hfr_fail(HFR_EDEVICE, "plan upload: %s", hipGetErrorString(e));
     }
     q->P = BatchDev{q->fields_d, q->tex_d, q->tex_start_d, q->mip_start_d, q->views_d, q->ray_start_d, q->queues_d,
-                    (int)n_tex, n_views, q->tuning.ray_tile_w};
+                    (int)n_tex, n_views, q->tuning.ray_tile_w, q->tuning.disc_grain};
     *out = q;
     return hfr_ok();
 }
@@ -310,6 +311,7 @@ extern "C" hfr_status hfr_batch_set_tuning(hfr_batch_plan* plan, const hfr_batch
         e = hipMemcpy(plan->views_d, plan->views_h, plan->views.size() * sizeof(BatchView), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hfr_fail(HFR_EDEVICE, "tuning upload: %s", hipGetErrorString(e));
     plan->P.tile_w = tuning->ray_tile_w;
+    plan->P.disc_grain = tuning->disc_grain;
     return hfr_ok();
 }
 

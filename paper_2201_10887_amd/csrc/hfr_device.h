@@ -198,7 +198,18 @@ struct BatchDev {
     const int* ray_start;  // [n_views + 1] prefix sums of 64-pixel tiles
     int* queues;           // HFR_QUEUE_WORDS counters, zeroed before each persistent launch
     int n_tex, n_views, tile_w;
+    int disc_grain;        // texel blocks per discretize queue access
 };
+
+// Read-only view of descriptor memory through the constant address space: the
+// descriptors do not change during a launch, and loads through this address
+// space with a wave-uniform index become scalar loads into scalar registers.
+template <class T>
+__device__ inline const T& as_constant(const T* p, int i)
+{
+    typedef __attribute__((address_space(4))) const T ConstT;
+    return *(const T*)((ConstT*)p + i);
+}
 
 hfr_status launch_discretize_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s);
 hfr_status launch_maxmip_batch(const BatchDev& P, const int* pass_blocks, hipStream_t s);
@@ -208,16 +219,23 @@ hfr_status launch_raycast_batch(const BatchDev& P, int blocks, bool backward, hi
 // into 8 contiguous chunks, one per XCD (the hardware deals workgroups to
 // the XCDs round-robin, so blockIdx.x & 7 names the workgroup's XCD; a
 // wrong guess only costs locality).  A caller starts with its own chunk and
-// moves to the next ones when it is exhausted, taking up to `grain`
-// consecutive indices per atomic: [*w0, *w1).  False when all queues are
+// moves to the next ones when it is exhausted.  Guided self-scheduling: a
+// grab takes a share of what is left in the chunk, remaining / (2 consumers),
+// clamped to [min_grain, max_grain], so early grabs are large (few atomics)
+// and the last ones small (an even finish); `consumers` is the number of
+// callers per XCD.  [*w0, *w1) is the range taken; false when all queues are
 // exhausted.  Each counter only grows, so every caller ends after at most 8
 // failed attempts.
-__device__ inline bool queue_grab(int* q, int total, int xcd, int grain, int* w0, int* w1)
+__device__ inline bool queue_grab(int* q, int total, int xcd, int min_grain, int max_grain, int consumers, int* w0,
+                                  int* w1)
 {
     for (int a = 0; a < 8; ++a) {
         const int c = (xcd + a) & 7;
         const int lo = (int)((int64_t)total * c / 8), hi = (int)((int64_t)total * (c + 1) / 8);
-        if (lo >= hi || __hip_atomic_load(&q[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo) continue;
+        const int taken = __hip_atomic_load(&q[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int left = hi - lo - taken;
+        if (left <= 0) continue;
+        const int grain = min(max(left / (2 * consumers), min_grain), max_grain);
         const int idx = lo + atomicAdd(&q[c], grain);
         if (idx < hi) {
             *w0 = idx;

@@ -570,13 +570,14 @@ __global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, T
 }
 
 // Persistent form over every cascade of every view of a batch: each
-// workgroup takes runs of DISC_GRAIN 16 x 16 texel blocks from the queues
+// workgroup takes runs of P.disc_grain 16 x 16 texel blocks from the queues
 // until all are done; the cascade a block belongs to is found by one search
-// per run and followed forward inside it.
-constexpr int DISC_GRAIN = 8;
+// per run and followed forward inside it.  The runs stay short: the blocks of
+// an XCD then work on neighbouring tiles at once and share node-table rows and
+// leaf records in its L2.
 
 template <bool BACKWARD>
-__global__ __launch_bounds__(256, BACKWARD ? 5 : 6) void discretize_batch_kernel(BatchDev P)
+__global__ __launch_bounds__(256, 7) void discretize_batch_kernel(BatchDev P)
 {
     __shared__ typename std::conditional<BACKWARD, DiscBwdShared, DiscShared>::type sh;
     __shared__ int work[3];
@@ -587,7 +588,7 @@ __global__ __launch_bounds__(256, BACKWARD ? 5 : 6) void discretize_batch_kernel
         __syncthreads();  // the previous run's LDS reads are done
         if (threadIdx.x == 0) {
             int w0 = -1, w1 = -1;
-            const bool got = queue_grab(q, total, xcd, DISC_GRAIN, &w0, &w1);
+            const bool got = queue_grab(q, total, xcd, P.disc_grain, P.disc_grain, 1, &w0, &w1);
             work[0] = got ? w0 : -1;
             work[1] = w1;
             work[2] = got ? find_item(P.tex_start, P.n_tex, w0) : 0;
@@ -604,8 +605,8 @@ __global__ __launch_bounds__(256, BACKWARD ? 5 : 6) void discretize_batch_kernel
                 item_lo = item_hi;
                 item_hi = P.tex_start[item + 1];
             }
-            const BatchTex& it = P.tex[item];
-            const BatchField& F = P.fields[it.field];
+            const BatchTex& it = as_constant(P.tex, item);
+            const BatchField& F = as_constant(P.fields, it.field);
             const int local = w - item_lo;
             const int bx = local % it.gx, by = local / it.gx;
             if constexpr (BACKWARD) discretize_backward_block(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs, sh);

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void maxmip_batch_kernel(BatchDev P, int p, in
             lo = hi;
             hi = start[item + 1];
         }
-        const BatchTex& it = P.tex[item];
+        const BatchTex& it = as_constant(P.tex, item);
         int lin, nlev, tiles;
         pass_shape(it.C.n, p, &lin, &nlev, &tiles);
         const int local = w - lo;

@@ -397,9 +397,8 @@ __global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __
 }
 
 // Persistent form over every view of a batch: each wave takes runs of
-// RAY_GRAIN 64-pixel tiles (tile_w x 64 / tile_w) from the queues until all
-// are done; waves never wait for each other.
-constexpr int RAY_GRAIN = 4;
+// 64-pixel tiles (tile_w x 64 / tile_w; guided: up to 32 early, down to 1 at
+// the end) from the queues until all are done; waves never wait for each other.
 
 template <bool BACKWARD>
 __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
@@ -411,7 +410,8 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
     const int tw = P.tile_w, th = 64 / tw;
     for (;;) {
         int w0 = -1, w1 = -1, v = 0;
-        if (lane == 0 && queue_grab(q, total, xcd, RAY_GRAIN, &w0, &w1)) v = find_item(P.ray_start, P.n_views, w0);
+        if (lane == 0 && queue_grab(q, total, xcd, 1, 32, max(1, (int)gridDim.x / 2), &w0, &w1))
+            v = find_item(P.ray_start, P.n_views, w0);
         // every lane is active here, so the first active lane is lane 0: the
         // values become wave-uniform (scalar registers, scalar descriptor loads)
         w0 = __builtin_amdgcn_readfirstlane(w0);
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
                 v_lo = v_hi;
                 v_hi = P.ray_start[v + 1];
             }
-            const BatchView& V = P.views[v];
+            const BatchView& V = as_constant(P.views, v);
             const int local = w - v_lo;
             const int tx = local % V.tiles_x, ty = local / V.tiles_x;
             raycast_pixel<BACKWARD>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,

@@ -229,7 +229,7 @@ def test_batch_arguments_rejected_before_any_device_call():
                                            0.0, 0.0, 100.0), dom
     _raise_einval("hfr_batch_plan_create", bad, 1, view(), 1, ctypes.byref(h))
     assert h.value is None
-    t = _lib.BatchTuning(4, 4, 12)
+    t = _lib.BatchTuning(4, 4, 12, 4)
     _raise_einval("hfr_batch_set_tuning", None, ctypes.byref(t))
     _raise_einval("hfr_batch_launch", None, None)
     _raise_einval("hfr_batch_launch_backward", None, None)

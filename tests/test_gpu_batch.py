@@ -215,9 +215,9 @@ def test_backward_matches_oracle(gpu, batch):
         assert per.mean() >= frac, per.mean()
 
 
-@pytest.mark.parametrize("tuning", [dict(disc_blocks_per_cu=1, ray_blocks_per_cu=1, ray_tile_w=64),
-                                    dict(disc_blocks_per_cu=8, ray_blocks_per_cu=2, ray_tile_w=16),
-                                    dict(disc_blocks_per_cu=2, ray_blocks_per_cu=8, ray_tile_w=32)])
+@pytest.mark.parametrize("tuning", [dict(disc_blocks_per_cu=1, ray_blocks_per_cu=1, ray_tile_w=64, disc_grain=1),
+                                    dict(disc_blocks_per_cu=8, ray_blocks_per_cu=2, ray_tile_w=16, disc_grain=64),
+                                    dict(disc_blocks_per_cu=2, ray_blocks_per_cu=8, ray_tile_w=32, disc_grain=3)])
 def test_tuning_does_not_change_results(gpu, batch, tuning):
     R, cams, _ = batch
     R.set_tuning()
