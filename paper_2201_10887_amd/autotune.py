@@ -113,11 +113,15 @@ def tune(renderer, cams: Sequence, backward: bool = True, grid: Optional[Dict[st
     entry = {"tuning": best["tuning"], "ms": best["ms"], "candidates": results}
     if cache_path:
         cache[key] = entry
-        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
-        tmp = cache_path + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(cache, f, indent=1)
-        os.replace(tmp, cache_path)
+        try:  # a read-only install still tunes; it only loses the cache
+            os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1)
+            os.replace(tmp, cache_path)
+        except OSError as e:
+            if log:
+                log(f"[autotune] cache not written: {e}")
     entry = dict(entry)
     entry["cached"] = False
     return entry

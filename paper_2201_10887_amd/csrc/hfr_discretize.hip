@@ -100,12 +100,6 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ inline float wave_sum(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // Visibility of the block's texels; returns this lane's texel visibility and
 // writes the block's 16-bit visibility half-words.  Block-uniform helpers
 // live in LDS: rxl / rxr (17 cell-row extents), mbits (16 rows).
@@ -295,6 +289,15 @@ __device__ inline bool reaches(const float4& q, float x0, float x1, float y0, fl
     return fmaf(dx, dx, dy * dy) < lim;
 }
 
+// Eq. 1 for one (texel, leaf) pair from the scaled offset: exp2(-r2) minus the
+// truncation constant, clipped at 0 (one subtract with the output clamp).
+// Subtracting per pair keeps long tile lists, where most pairs lie beyond the
+// cutoff, from cancelling a large sum of constants at the end.
+__device__ __forceinline__ float rbf_weight(float dx, float dy, float E)
+{
+    return __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)) - E, 0.0f, 1.0f);
+}
+
 struct TileFrame {
     float x0, x1, y0, y1;  // tile rectangle relative to the block origin
     float npx, npy;        // minus the lane's texel centre relative to the block origin
@@ -352,8 +355,7 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const float lim = T.T2 * 1.0001f, E = T.E;
     float4* trec = sh.trec_all[wave];
-    float s0 = 0.0f, s1 = 0.0f, vpart = 0.0f;
-    int n_eval = 0;
+    float s0 = 0.0f, s1 = 0.0f;
     const int n_el = block_levels(T, br, sh.scan);
     for (int lo = 0;; lo += BCAP) {
         const int total = block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
@@ -372,19 +374,14 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
                     wave_sync();
                     for (int a = 0; a < nt; ++a) {
                         const float4 r = trec[a];
-                        const float dx = fmaf(f.npx, r.z, r.x), dy = fmaf(f.npy, r.z, r.y);
-                        const float g = fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)), E);
+                        const float g = rbf_weight(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
                         s0 += g;
                         s1 = fmaf(g, r.w, s1);
                     }
-                    n_eval += nt;
                     nt = 0;
                     wave_sync();
                 }
-                if (keep) {
-                    trec[nt + __popcll(m & lt)] = q;
-                    vpart += q.w;
-                }
+                if (keep) trec[nt + __popcll(m & lt)] = q;
                 nt += k;
             }
             wave_sync();
@@ -393,33 +390,25 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float4 r = trec[a + u];
-                    const float dx = fmaf(f.npx, r.z, r.x), dy = fmaf(f.npy, r.z, r.y);
-                    const float g = fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)), E);
+                    const float g = rbf_weight(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
                     s0 += g;
                     s1 = fmaf(g, r.w, s1);
                 }
             }
             for (; a < nt; ++a) {
                 const float4 r = trec[a];
-                const float dx = fmaf(f.npx, r.z, r.x), dy = fmaf(f.npy, r.z, r.y);
-                const float g = fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)), E);
+                const float g = rbf_weight(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
                 s0 += g;
                 s1 = fmaf(g, r.w, s1);
             }
-            n_eval += nt;
             wave_sync();
         }
         if (lo + BCAP >= total) break;
         __syncthreads();
     }
-    const float vsum = wave_sum(vpart);  // every lane of the wave takes part
     if (!inside) return;
     float out = -INFINITY;
-    if (vis) {
-        const float S0 = s0 - (float)n_eval * E;
-        const float S1 = s1 - E * vsum;
-        out = S0 > 0.0f ? S1 / S0 : NAN;
-    }
+    if (vis) out = s0 > 0.0f ? s1 / s0 : NAN;
     tex[(int64_t)j * N + i] = out;
 }
 

@@ -1,0 +1,156 @@
+"""GPU parity at the large scene's full size (64.1M leaves, 4 x 4096^2 cascades, 3840 x 2160).
+
+The GPU runs every kernel over the whole frame; the oracle recomputes seeded
+samples: the library's quadtree against the oracle's at full size, visibility
+over every texel, texel values in sampled windows (the oracle's Eq. 2 over
+every leaf that can reach the window, selected by an exact distance test),
+the max-mipmap bit-exact, and sampled rays and their texel gradients on
+stand-in textures.  The raster comes from the seeded generator run in torch
+on the GPU (the same generator, minutes faster than NumPy at 16384^2).
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint, cascades as ocas, discretize as odisc, maxmip as omip, quadtree as oqt, raycast as oray
+from paper_2201_10887_amd import api, synth
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+THREADS = 16
+
+
+def _say(msg):
+    print(f"[large] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def large(gpu):
+    w = synth.LARGE
+    dem = synth.fbm_dem(w.dem_n, w.octaves, w.hurst, w.seed, mountains=w.mountains, device="cuda")
+    _say("raster done; oracle quadtree")
+    leaves = oqt.build_quadtree(dem, w.side, w.max_depth, w.tau)
+    _say(f"{len(leaves['x'])} leaves; cascades, node table, visibility")
+    leaves["sigma"] = np.full(len(leaves["x"]), w.sigma, np.float32)
+    dom = synth.Domain(0.0, 0.0, w.side, w.side, float(leaves["v"].min()), float(leaves["v"].max()))
+    cam = synth.camera_of(w, dem)
+    cs = ocas.fit_cascades(cam, dom, w.cascades, w.tex_n, w.split_lambda, w.overlap, float(leaves["c"].min()))
+    node = api.build_node_table(leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(leaves, node, w.side, w.max_depth, w.cutoff)
+    api.pack_leaves(L)
+    del node
+    vis = [odisc.visibility(c) for c in cs]  # every texel of every cascade
+    _say("scene ready")
+    return dict(w=w, dem=dem, leaves=leaves, dom=dom, cam=cam, cs=cs, L=L, cas=api.cascades_from(cs), vis=vis)
+
+
+def test_scene_size(large):
+    n = len(large["leaves"]["x"])
+    assert 60e6 < n < 68e6, n
+
+
+def test_library_quadtree_matches_at_full_size(large):
+    w = large["w"]
+    got = api.build_quadtree(large["dem"], w.side, w.max_depth, w.tau)
+    for k in ("x", "y", "c", "v", "level", "i", "j"):
+        assert np.array_equal(got[k], large["leaves"][k]), k
+
+
+def _reaching(leaves, cutoff, box):
+    """Indices of every leaf whose truncation radius reaches the closed box (exact test, FP64)."""
+    x = leaves["x"].astype(np.float64)
+    y = leaves["y"].astype(np.float64)
+    r = cutoff * leaves["sigma"].astype(np.float64) * leaves["c"].astype(np.float64) * 1.001
+    dx = np.maximum(np.maximum(box[0] - x, x - box[2]), 0.0)
+    dy = np.maximum(np.maximum(box[1] - y, y - box[3]), 0.0)
+    return np.nonzero(dx * dx + dy * dy < r * r)[0]
+
+
+def test_discretize_full_frame_sampled(gpu, large):
+    m = large
+    w = m["w"]
+    K, N = len(m["cas"]), m["cas"][0].n
+    mask = gpu.zeros((K, N, (N + 31) // 32), dtype=gpu.int32, device="cuda")
+    tex = api.discretize(m["L"], m["dom"], m["cas"], mask=mask).cpu().numpy()
+    bits = mask.cpu().numpy().view(np.uint32)
+    vis_gpu = ((bits[:, :, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(K, N, -1)[:, :, :N].astype(bool)
+    assert np.array_equal(vis_gpu, np.isfinite(tex))
+    assert not np.isnan(tex).any()
+    rng = np.random.default_rng(2025)
+    for k, cas in enumerate(m["cs"]):
+        vis = m["vis"][k]
+        assert np.array_equal(vis, vis_gpu[k]), f"cascade {k}: {np.argwhere(vis != vis_gpu[k])[:5]}"
+        jj, ii = np.nonzero(vis)
+        for _ in range(3):  # 48 x 48 texel windows around random visible texels
+            a = rng.integers(len(jj))
+            j0, i0 = max(jj[a] - 24, 0), max(ii[a] - 24, 0)
+            wj, wi = np.nonzero(vis[j0:j0 + 48, i0:i0 + 48])
+            sj, si = (wj + j0).astype(np.int64), (wi + i0).astype(np.int64)
+            p = odisc.clamp_to_domain(odisc.texel_centres(cas, si, sj), m["dom"])
+            box = (p[:, 0].min(), p[:, 1].min(), p[:, 0].max(), p[:, 1].max())
+            sub = _reaching(m["leaves"], w.cutoff, box)
+            field = odisc.RBFField({key: m["leaves"][key][sub] for key in ("x", "y", "c", "v", "sigma")}, w.cutoff)
+            ref, _ = field.evaluate(p)
+            got = tex[k][sj, si]
+            tol = G.texel_tolerance(m["leaves"], ref)
+            err = np.abs(got - ref)
+            assert np.all(err <= tol), f"cascade {k}: max error {err.max()} at {np.argmax(err - tol)}"
+
+
+@pytest.fixture(scope="module")
+def standin(gpu, large):
+    """Stand-in textures of the full frame: the raster sampled at the texels, -inf where invisible."""
+    m = large
+    tex = np.stack([synth.resample_raster(m["dem"], m["w"].side, c.x0, c.y0, c.hx, c.hy, c.n) for c in m["cs"]])
+    for k in range(len(m["cs"])):
+        tex[k][~m["vis"][k]] = -np.inf
+    return tex
+
+
+def test_maxmip_full_size_bitexact(gpu, standin):
+    mip = api.build_maxmip(gpu.as_tensor(standin, device="cuda")).cpu().numpy()
+    for k in range(len(standin)):
+        assert np.array_equal(mip[k], omip.flatten(omip.maxmip(standin[k])).astype(np.float32))
+
+
+def test_raycast_full_frame_sampled(gpu, large, standin):
+    m = large
+    tex = gpu.as_tensor(standin, device="cuda")
+    mip = api.build_maxmip(tex)
+    depth, hit = api.raycast(m["cam"], m["dom"], m["cas"], tex, mip)
+    depth, hit = depth.cpu().numpy().ravel(), hit.cpu().numpy().ravel()
+    cam = m["cam"]
+    rng = np.random.default_rng(8)
+    pix = rng.choice(cam.width * cam.height, 100_000, replace=False)
+    ref = oray.raycast(cam, m["dom"], m["cs"], standin, cols=pix % cam.width, rows=pix // cam.width,
+                       threads=THREADS)
+    G.compare_hits(depth[pix], hit[pix], ref, cam, m["dom"], m["cs"], standin, what="large raycast")
+    assert np.isfinite(ref["depth"]).mean() > 0.3
+
+
+def test_raycast_backward_full_frame_sampled(gpu, large, standin):
+    m = large
+    cam = m["cam"]
+    K, N = len(m["cas"]), m["cas"][0].n
+    tex = gpu.as_tensor(standin, device="cuda")
+    mip = api.build_maxmip(tex)
+    rng = np.random.default_rng(10)
+    pix = rng.choice(cam.width * cam.height, 30_000, replace=False)
+    ref = oray.raycast(cam, m["dom"], m["cs"], standin, cols=pix % cam.width, rows=pix // cam.width,
+                       threads=THREADS)
+    g_pix = rng.normal(0, 1, len(pix)) * np.isfinite(ref["depth"])
+    gd = np.zeros(cam.width * cam.height, np.float32)
+    gd[pix] = g_pix
+    g_ref = adjoint.texel_gradients(ref, g_pix, K, N)
+    g_gpu = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip,
+                                 gpu.as_tensor(gd.reshape(cam.height, cam.width), device="cuda")).cpu().numpy()
+    err, per = G.grad_close(g_gpu, g_ref)
+    assert err <= 1e-3 and per.mean() >= 0.999, (err, per.mean())
