@@ -83,7 +83,7 @@ def discretize_work(R, cas, leaves, w, samples=20000) -> dict:
     exp2, the truncation subtraction and clamp, and a fused multiply-add plus
     an add for the two sums.  The pair count is the visible-texel count times
     the mean number of influencing leaves of a seeded sample of visible
-    texels (counted in FP64 over the node table's windows, level by level).
+    texels (counted in FP64 over lattice windows of the level index, level by level).
     Bytes: every texel's FP32 value and visibility bit written once, and the
     16-byte record of every leaf within reach of a cascade's polygon read once.
     """
@@ -98,7 +98,7 @@ def discretize_work(R, cas, leaves, w, samples=20000) -> dict:
     y = leaves["y"].astype(np.float64)
     c = leaves["c"].astype(np.float64)
     sg = leaves["sigma"].astype(np.float64)
-    node = R.L.node.cpu().numpy()
+    rank, order = R.L.rank.cpu().numpy(), R.L.order.cpu().numpy()
     rng = np.random.default_rng(11)
     kk, jj, ii = np.nonzero(vis)
     pick = rng.choice(len(kk), min(samples, len(kk)), replace=False)
@@ -125,7 +125,9 @@ def discretize_work(R, cas, leaves, w, samples=20000) -> dict:
         I = gi[:, None, None] + off[None, None, :]
         J = gj[:, None, None] + off[None, :, None]
         ok = (I >= 0) & (I < S) & (J >= 0) & (J < S)
-        ids = np.where(ok, node[(4 ** l - 1) // 3 + np.clip(J, 0, S - 1) * S + np.clip(I, 0, S - 1)], -1)
+        cell = api.rank_offset(l) + np.clip(J, 0, S - 1) * S + np.clip(I, 0, S - 1)
+        leaf_at = ok & (rank[cell + 1] > rank[cell])
+        ids = np.where(leaf_at, order[np.minimum(rank[cell], len(order) - 1)], -1)
         a_idx, lst = np.nonzero(ids.reshape(len(pick), -1) >= 0)
         lid = ids.reshape(len(pick), -1)[a_idx, lst]
         q = np.hypot(x[lid] - px[a_idx], y[lid] - py[a_idx]) / (sg[lid] * c[lid])

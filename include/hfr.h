@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 3
+#define HFR_ABI_VERSION 4
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -95,16 +95,16 @@ typedef struct {
  * [x0, x0 + side] x [y0, y0 + side], levels 0 .. max_depth.
  *  x, y, c, v, sigma : float[n]   centre, cell size, value, Gaussian width
  *                                 (in units of the cell size)
- *  packed            : float[4n]  (x, y, v, s) per leaf, written by
+ *  packed            : float[4n]  (x, y, v, s) per leaf in level-index order
+ *                                 (packed[p] is leaf order[p]), written by
  *                                 hfr_pack_leaves; s = sqrt(log2(e) / 2) / (sigma c),
  *                                 so that Eq. 1's Gaussian is exp2(-(s r)^2)
  *  level_radius      : float[max_depth + 1], written by hfr_pack_leaves: the
  *                      largest truncation radius cutoff * sigma_j * c_j of the
  *                      leaves of each level (0 where a level has none)
- *  node              : int32[(4^(max_depth+1) - 1) / 3], hfr_build_node_table:
- *                      the leaf index of every lattice node, level by level
- *                      (level l at offset (4^l - 1) / 3, row-major 2^l x 2^l,
- *                      row = y), -1 for nodes that are not leaves
+ *  rank, order       : the level index written by hfr_build_level_index (host
+ *                      arrays copied to the device); packed is stored in the
+ *                      order it defines
  *  cutoff            : truncation radius in units of sigma (the paper's 3.5)
  */
 typedef struct {
@@ -116,7 +116,8 @@ typedef struct {
     const float* sigma;
     float* packed;
     float* level_radius;
-    const int32_t* node;
+    const int32_t* rank;
+    const int32_t* order;
     int32_t max_depth;
     float cutoff;
     double x0, y0, side;
@@ -172,15 +173,20 @@ hfr_status hfr_neighbours_size(const hfr_neighbours* nb, int64_t* nnz);
 hfr_status hfr_neighbours_export(const hfr_neighbours* nb, int32_t* off, int32_t* idx);
 void hfr_neighbours_destroy(hfr_neighbours* nb);
 
-/* Dense lattice index of the leaves: host node[(4^(max_depth+1) - 1) / 3],
- * the leaf index at every (level, i, j) node, -1 where the node is not a
- * leaf (layout as in hfr_leaves.node).  Same lattice requirements as
- * hfr_build_neighbours; EINVAL if the leaves do not tile the square exactly
- * once or max_depth > 15.  It replaces per-cell influence buffers on the
- * device: the influencers of any region are found by scanning, per level,
- * the lattice window within that level's truncation radius. */
-hfr_status hfr_build_node_table(int64_t n, const float* x, const float* y, const float* c, double x0,
-                                double y0, double side, int32_t max_depth, int32_t* node);
+/* Level index of the leaves (host arrays).  Leaves are ordered by level,
+ * then lattice row j (y), then column i (x): order[p] is the leaf at sorted
+ * position p (int32[n]).  rank holds, for every level l, 4^l + 1 exclusive
+ * prefix counts at offset (4^l - 1) / 3 + l (int32[(4^(max_depth+1) - 1) / 3
+ * + max_depth + 1] in all): rank[off_l + j 2^l + i] is the sorted position of
+ * the first level-l leaf at or after node (i, j) in row-major order (the
+ * leaves of all coarser levels come first).  The level-l leaves of lattice
+ * row j with columns ia..ib are therefore the sorted positions
+ * [rank[off_l + j 2^l + ia], rank[off_l + j 2^l + ib + 1]), so the influencers
+ * of a region are found per level and row without visiting empty nodes.
+ * Same lattice requirements as hfr_build_neighbours; EINVAL if the leaves do
+ * not tile the square exactly once, max_depth > 15 or n > INT32_MAX. */
+hfr_status hfr_build_level_index(int64_t n, const float* x, const float* y, const float* c, double x0,
+                                 double y0, double side, int32_t max_depth, int32_t* rank, int32_t* order);
 
 /* --------------------------------------------------------- per frame (host) */
 
@@ -204,9 +210,9 @@ hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_
 
 /* ------------------------------------------------------- per frame (device) */
 
-/* Writes L->packed and L->level_radius from x, y, v, c, sigma and cutoff
- * (call again whenever v or sigma change).  EINVAL on NULL pointers,
- * n < 1, cutoff <= 0, max_depth outside [0, 15]. */
+/* Writes L->packed (gathered through L->order) and L->level_radius from x,
+ * y, v, c, sigma and cutoff (call again whenever v or sigma change).  EINVAL
+ * on NULL pointers, n < 1, cutoff <= 0, max_depth outside [0, 15]. */
 hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
 
 /* Discretization (Section 4, Eq. 1 and Eq. 2, and the visibility texture of
@@ -216,7 +222,7 @@ hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
  *   v_s = sum_j w_j v_j / sum_j w_j,
  *   w_j = max(0, exp(-(|p_j - p_s| / (sigma_j c_j))^2 / 2) - exp(-cutoff^2 / 2)),
  * evaluated at the texel centre clamped into the domain, summed over every
- * leaf with w_j > 0 (found per tile of texels from L->node and
+ * leaf with w_j > 0 (found per block of texels from L->rank and
  * L->level_radius); an invisible texel holds -inf.  tex: device float[K][N][N].  mask: device uint32
  * [K][N][(N + 31) / 32] visibility bits (bit i % 32 of word i / 32), or NULL.
  * A texel no leaf influences (impossible when cutoff sigma_j > sqrt(2)/2 for
@@ -299,7 +305,7 @@ hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
 typedef struct hfr_batch_plan hfr_batch_plan;
 
 /* One heightfield.  leaves: as for hfr_discretize (packed records, level
- * radii and node table already built; sigma is needed for the backward
+ * radii and level index already built; sigma is needed for the backward
  * pass).  dom: its domain.  grad_v, grad_sigma: device float[leaves.n]
  * written by hfr_batch_launch_backward (summed over every view of this
  * field), or NULL when the plan has no backward pass. */

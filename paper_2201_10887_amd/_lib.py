@@ -47,7 +47,8 @@ class Cascade(ctypes.Structure):
 class Leaves(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("c", ctypes.c_void_p),
                 ("v", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("packed", ctypes.c_void_p),
-                ("level_radius", ctypes.c_void_p), ("node", ctypes.c_void_p), ("max_depth", ctypes.c_int32),
+                ("level_radius", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("max_depth", ctypes.c_int32),
                 ("cutoff", ctypes.c_float), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
                 ("side", ctypes.c_double)]
 
@@ -89,7 +90,7 @@ SIGNATURES = {
     "hfr_neighbours_size": ([P, PP(I64)], I32),
     "hfr_neighbours_export": ([P, P, P], I32),
     "hfr_neighbours_destroy": ([P], None),
-    "hfr_build_node_table": ([I64, P, P, P, F64, F64, F64, I32, P], I32),
+    "hfr_build_level_index": ([I64, P, P, P, F64, F64, F64, I32, P, P], I32),
     "hfr_fit_cascades": ([PP(Camera), PP(Domain), I32, I32, F64, F64, F64, PP(Cascade)], I32),
     "hfr_pack_leaves": ([PP(Leaves), P], I32),
     "hfr_discretize": ([PP(Leaves), PP(Domain), PP(Cascade), I32, P, P, P], I32),

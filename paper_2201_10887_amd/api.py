@@ -148,15 +148,23 @@ def build_neighbours(leaves: dict, side: float, max_depth: int, cutoff: float, s
     return off, idx
 
 
-def node_table_size(max_depth: int) -> int:
-    return ((1 << (2 * (max_depth + 1))) - 1) // 3
+def rank_table_size(max_depth: int) -> int:
+    return ((1 << (2 * (max_depth + 1))) - 1) // 3 + max_depth + 1
 
 
-def build_node_table(leaves: dict, side: float, max_depth: int, x0: float = 0.0, y0: float = 0.0) -> np.ndarray:
+def rank_offset(level: int) -> int:
+    """Offset of a level's 4^level + 1 prefix counts in the rank table."""
+    return ((1 << (2 * level)) - 1) // 3 + level
+
+
+def build_level_index(leaves: dict, side: float, max_depth: int, x0: float = 0.0, y0: float = 0.0):
+    """``(rank, order)``: the leaves sorted by (level, row, column) and per-level prefix counts."""
     arrs = [np.ascontiguousarray(leaves[k], np.float32) for k in ("x", "y", "c")]
-    node = np.empty(node_table_size(max_depth), np.int32)
-    call("hfr_build_node_table", len(arrs[0]), *(_np_ptr(a) for a in arrs), x0, y0, side, max_depth, _np_ptr(node))
-    return node
+    rank = np.empty(rank_table_size(max_depth), np.int32)
+    order = np.empty(len(arrs[0]), np.int32)
+    call("hfr_build_level_index", len(arrs[0]), *(_np_ptr(a) for a in arrs), x0, y0, side, max_depth,
+         _np_ptr(rank), _np_ptr(order))
+    return rank, order
 
 
 def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: float) -> ctypes.Array:
@@ -168,17 +176,19 @@ def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: fl
 # ---------------------------------------------------------- per frame (device)
 
 class DeviceLeaves:
-    """Leaf arrays, node table and per-level radii resident on the GPU (torch tensors)."""
+    """Leaf arrays, level index and per-level radii resident on the GPU (torch tensors)."""
 
-    def __init__(self, leaves: dict, node: np.ndarray, side: float, max_depth: int, cutoff: float,
+    def __init__(self, leaves: dict, index, side: float, max_depth: int, cutoff: float,
                  x0: float = 0.0, y0: float = 0.0, device: str = "cuda"):
         import torch
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
         self.x, self.y, self.c = f(leaves["x"]), f(leaves["y"]), f(leaves["c"])
         self.v, self.sigma = f(leaves["v"]), f(leaves["sigma"])
-        if len(node) != node_table_size(max_depth):
-            raise ValueError("node table size does not match max_depth")
-        self.node = torch.as_tensor(np.ascontiguousarray(node, np.int32), device=device)
+        rank, order = index
+        if len(rank) != rank_table_size(max_depth) or len(order) != len(leaves["x"]):
+            raise ValueError("level index does not match max_depth and the leaf count")
+        self.rank = torch.as_tensor(np.ascontiguousarray(rank, np.int32), device=device)
+        self.order = torch.as_tensor(np.ascontiguousarray(order, np.int32), device=device)
         self.n = len(leaves["x"])
         self.packed = torch.empty((self.n, 4), dtype=torch.float32, device=device)
         self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=device)
@@ -189,10 +199,12 @@ class DeviceLeaves:
         import torch
         for name in ("x", "y", "c", "v", "sigma", "packed", "level_radius"):
             _dev(getattr(self, name), torch.float32, None, name)
-        _dev(self.node, torch.int32, None, "node")
+        _dev(self.rank, torch.int32, None, "rank")
+        _dev(self.order, torch.int32, (self.n,), "order")
         return Leaves(self.n, self.x.data_ptr(), self.y.data_ptr(), self.c.data_ptr(), self.v.data_ptr(),
                       self.sigma.data_ptr(), self.packed.data_ptr(), self.level_radius.data_ptr(),
-                      self.node.data_ptr(), self.max_depth, self.cutoff, self.x0, self.y0, self.side)
+                      self.rank.data_ptr(), self.order.data_ptr(), self.max_depth, self.cutoff, self.x0, self.y0,
+                      self.side)
 
 
 def pack_leaves(L: DeviceLeaves, stream=None) -> None:

@@ -1,6 +1,6 @@
 """Many views of many heightfields per launch (libhfr's ``hfr_batch_*``).
 
-``Field`` is one device-resident heightfield (leaves, node table, per-level
+``Field`` is one device-resident heightfield (leaves, level index, per-level
 radii, leaf gradients).  ``BatchRenderer`` allocates every view's buffers
 once, creates the library plan and runs the batched forward and backward
 passes on the current stream; ``capture`` records both into one
@@ -22,8 +22,8 @@ class Field:
     def __init__(self, leaves: dict, side: float, max_depth: int, cutoff: float, x0: float = 0.0, y0: float = 0.0,
                  device: str = "cuda", with_grads: bool = True):
         import torch
-        node = api.build_node_table(leaves, side, max_depth, x0, y0)
-        self.L = api.DeviceLeaves(leaves, node, side, max_depth, cutoff, x0, y0, device=device)
+        index = api.build_level_index(leaves, side, max_depth, x0, y0)
+        self.L = api.DeviceLeaves(leaves, index, side, max_depth, cutoff, x0, y0, device=device)
         api.pack_leaves(self.L)
         self.dom = _Dom(x0, y0, x0 + side, y0 + side, float(np.min(leaves["v"])), float(np.max(leaves["v"])))
         self.c_min = float(np.min(leaves["c"]))

@@ -126,9 +126,10 @@ struct Dom2 {
 
 // Leaf data and constants of one heightfield, as the texture kernels read them.
 struct Tables {
-    const float4* packed;
+    const float4* packed;   // level-index order
     const float* radius;
-    const int32_t* node;
+    const int32_t* rank;    // level index: exclusive prefix counts per level
+    const int32_t* order;   // leaf index of each sorted position
     const float* sigma;
     int n, max_depth;
     double x0, y0, side, inv_side;

@@ -8,23 +8,25 @@
 //  1. Visibility: the 17 cell rows touching the block get their polygon
 //     x-extent in LDS; every texel tests its incident cells; the block's
 //     16-bit halves of the visibility words are assembled with LDS atomics.
-//  2. Block scan (all 256 lanes): per quadtree level, the lattice window
-//     within that level's largest truncation radius of the block rectangle
-//     is read from the dense node table (several independent loads in
-//     flight per lane); leaves whose centre is within the radius are
-//     appended in a fixed order (per-wave ballots and a 4-entry prefix).
-//  3. The block's leaf records are gathered once into LDS as (s x, s y, s, v),
-//     positions relative to the block origin (FP64 difference, then FP32),
-//     with s = sqrt(log2(e) / 2) / (sigma c) so that Eq. 1's Gaussian is
-//     exp2(-(s r)^2).
+//  2. Candidate search (all 256 lanes): per quadtree level, the lattice rows
+//     and columns within that level's largest truncation radius of the block
+//     rectangle.  The level index turns each window row into one range of
+//     sorted leaf positions (two reads of the rank table per row), so only
+//     leaves are visited, never empty lattice nodes.  A block-wide prefix of
+//     the row lengths flattens the rows into one element range.
+//  3. Element ranges of BCAP are gathered in order: every leaf whose own
+//     truncation radius reaches the block rectangle goes to LDS as
+//     (s x, s y, s, v), positions relative to the block origin (FP64
+//     difference, then FP32), with s = sqrt(log2(e) / 2) / (sigma c) so that
+//     Eq. 1's Gaussian is exp2(-(s r)^2).
 //  4. Each wave keeps the records whose own truncation radius reaches its
 //     tile (a compact copy in LDS), and every lane (texel) runs Eq. 1 / Eq. 2
-//     over them with broadcast LDS reads and immediate offsets.  The inner
-//     loop sums max(g, E) and max(g, E) v; the constant E of the truncated
-//     Gaussian is subtracted once per tile list (E times the list length and
-//     E times the sum of its values), which is the same sum as
-//     sum max(g - E, 0) and sum max(g - E, 0) v.
-// More candidates than fit in LDS are handled in rounds (rescan, next slice).
+//     over them with broadcast LDS reads and immediate offsets, subtracting
+//     the truncation constant per pair.
+// Candidates beyond one element range are handled in rounds (the next range);
+// windows of more than RCAP rows in chunks.  The order in which leaves reach
+// a texel's sums is (level, row, column) whatever the rounds, so results do
+// not depend on them.
 #include <cmath>
 #include <type_traits>
 
@@ -35,9 +37,9 @@ namespace {
 constexpr int BS = 16;        // block side in texels
 constexpr int TS = 8;         // tile side in texels (one wave)
 constexpr int WAVES = 4;      // 2 x 2 tiles per block
-constexpr int BCAP = 512;     // block candidates staged per round
+constexpr int BCAP = 512;     // candidate elements gathered per round (two per lane)
 constexpr int TCAP = 128;     // tile-list records per chunk
-constexpr int UNROLL = 2;     // node-table loads in flight per lane during the scan
+constexpr int RCAP = 256;     // window rows per chunk (one per lane)
 constexpr float LOG2E = 1.4426950408889634f;
 
 
@@ -48,21 +50,24 @@ struct Rect {
     double x0, y0, x1, y1;
 };
 
-// Packs leaf records and finds, per quadtree level, the largest support
-// radius.  The per-level maxima are reduced in LDS first so that each block
-// issues at most max_depth + 1 global atomics (one per level it saw).
+// Packs leaf records in level-index order (record p is leaf order[p]) and
+// finds, per quadtree level, the largest support radius.  The per-level
+// maxima are reduced in LDS first so that each block issues at most
+// max_depth + 1 global atomics (one per level it saw).
 __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restrict__ x, const float* __restrict__ y,
                                                           const float* __restrict__ v, const float* __restrict__ c,
-                                                          const float* __restrict__ sigma, float cutoff, float side,
+                                                          const float* __restrict__ sigma,
+                                                          const int32_t* __restrict__ order, float cutoff, float side,
                                                           int max_depth, float4* __restrict__ out,
                                                           float* __restrict__ radius, int64_t n)
 {
     __shared__ int level_max[16];  // max_depth <= 15; positive floats order as ints, 0 = no leaf seen
     if (threadIdx.x < 16) level_max[threadIdx.x] = 0;
     __syncthreads();
-    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int a = order[p];
         const float sc = sigma[a] * c[a];
-        out[a] = make_float4(x[a], y[a], v[a], sqrtf(HALF_LOG2E) / sc);
+        out[p] = make_float4(x[a], y[a], v[a], sqrtf(HALF_LOG2E) / sc);
         int l = (int)rintf(log2f(side / c[a]));
         l = min(max(l, 0), max_depth);
         const float R = cutoff * sc * 1.00001f;
@@ -139,145 +144,161 @@ __device__ inline bool block_visibility(const TexCascade& C, int bi0, int bj0, i
     return vis;
 }
 
-// Lattice window of one quadtree level around a block rectangle.
+// Window of one quadtree level around a block rectangle: columns [ia, ib]
+// of lattice rows ja, ja + 1, ... of the level.
 struct LevelWin {
-    double c, R2;  // cell size, squared truncation radius
-    int64_t off;   // offset of the level in the node table
-    int start;     // first element of this level in the flattened (level, element) order
-    int ia, ja, wi, S;
-    float inv_w;
+    int64_t off;  // offset of the level in the rank table
+    int ia, ib, ja, S;
 };
 constexpr int MAX_LEVELS = 16;
 
 struct ScanShared {
     LevelWin lw[MAX_LEVELS];
-    int start[MAX_LEVELS + 1];
-    int wcnt[WAVES];
+    int rstart[MAX_LEVELS + 1];  // first flattened window row of each level
+    int seg_pos[RCAP];           // sorted position of the first leaf of each row of the chunk
+    int seg_off[RCAP + 1];       // first element of each row of the chunk
+    int wcnt[2][WAVES];          // per-wave counts (two buffers: consecutive prefixes need no barrier between)
 };
 
-// Windows of every level around the block rectangle (thread l fills level l),
-// flattened into one element range: level l owns [start[l], start[l + 1]).
-// Returns the total element count (block-uniform).
-__device__ int block_levels(const Tables& T, const Rect& r, ScanShared& sc)
+// Windows of every level around the block rectangle (thread l fills level l):
+// the lattice nodes within the level's largest truncation radius of the
+// rectangle, widened by one node on each side.  Returns the number of window
+// rows over all levels (block-uniform).
+__device__ int block_rows(const Tables& T, const Rect& r, ScanShared& sc)
 {
     const int t = threadIdx.x;
     if (t <= T.max_depth) {
         const int l = t;
         LevelWin w{};
-        int cnt = 0;
+        int rows = 0;
         const float Rf = T.radius[l];
         if (Rf > 0.0f) {
             const double R = Rf;
-            const double c = ldexp(T.side, -l), inv_c = ldexp(T.inv_side, l);
+            const double inv_c = ldexp(T.inv_side, l);
             const int S = 1 << l;
             const int ia = max(0, (int)floor((r.x0 - R - T.x0) * inv_c - 0.5) - 1);
             const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) * inv_c - 0.5) + 1);
             const int ja = max(0, (int)floor((r.y0 - R - T.y0) * inv_c - 0.5) - 1);
             const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) * inv_c - 0.5) + 1);
-            const int wi = ib - ia + 1, hj = jb - ja + 1;
-            if (wi > 0 && hj > 0) {
-                cnt = wi * hj;
-                w = LevelWin{c, R * R, ((int64_t(1) << (2 * l)) - 1) / 3, 0, ia, ja, wi, S, 1.0f / (float)wi};
+            if (ib >= ia && jb >= ja) {
+                rows = jb - ja + 1;
+                w = LevelWin{((int64_t(1) << (2 * l)) - 1) / 3 + l, ia, ib, ja, S};
             }
         }
         sc.lw[l] = w;
-        sc.start[l + 1] = cnt;
+        sc.rstart[l + 1] = rows;
     }
     __syncthreads();
     if (t == 0) {
         int acc = 0;
         for (int l = 0; l <= T.max_depth; ++l) {
-            const int cnt = sc.start[l + 1];
-            sc.start[l] = acc;
-            sc.lw[l].start = acc;
-            acc += cnt;
+            const int rows = sc.rstart[l + 1];
+            sc.rstart[l] = acc;
+            acc += rows;
         }
-        for (int l = T.max_depth + 1; l <= MAX_LEVELS; ++l) sc.start[l] = acc;
+        for (int l = T.max_depth + 1; l <= MAX_LEVELS; ++l) sc.rstart[l] = acc;
     }
     __syncthreads();
-    return sc.start[MAX_LEVELS];
+    return sc.rstart[MAX_LEVELS];
 }
 
-// Cooperative block scan over the flattened windows: every leaf whose centre
-// is closer than its level's radius to the block rectangle, in the fixed
-// order (level, element); indices with rank in [lo, lo + BCAP) go to bids.
-// Returns the total count (block-uniform).  Every wave of the block must call
-// it, after block_levels.
-__device__ int block_scan(const Tables& T, const Rect& r, int n_el, int lo, int* bids, ScanShared& sc, int wave,
-                          int lane)
+// Window rows [r0, r0 + RCAP): lane t reads the sorted-position range of row
+// r0 + t from the rank table; seg_off becomes the exclusive prefix of the
+// row lengths.  Returns the chunk's element count (block-uniform).
+__device__ int chunk_rows(const Tables& T, ScanShared& sc, int r0, int n_rows, int wave, int lane)
+{
+    __syncthreads();  // nobody reads the previous chunk's rows any more
+    const int r = r0 + (int)threadIdx.x;
+    int pos = 0, len = 0;
+    if (r < n_rows) {
+        // the level owning row r: the largest l with rstart[l] <= r (an empty
+        // level shares its successor's start, so the largest such l owns rows)
+        int l = 0;
+#pragma unroll
+        for (int step = MAX_LEVELS / 2; step > 0; step >>= 1)
+            if (sc.rstart[l + step] <= r) l += step;
+        const LevelWin& w = sc.lw[l];
+        const int64_t row = w.off + (int64_t)(w.ja + r - sc.rstart[l]) * w.S;
+        pos = T.rank[row + w.ia];
+        len = T.rank[row + w.ib + 1] - pos;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) sc.wcnt[0][wave] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const int k = sc.wcnt[0][w];
+        before += w < wave ? k : 0;
+        all += k;
+    }
+    sc.seg_pos[threadIdx.x] = pos;
+    sc.seg_off[threadIdx.x] = before + incl - len;
+    if (threadIdx.x == 0) sc.seg_off[RCAP] = all;
+    __syncthreads();
+    return all;
+}
+
+// Elements [e0, e0 + BCAP) of the chunk, 256 at a time (lane t takes one
+// element of each): every leaf whose own truncation radius reaches the block
+// rectangle goes to brec as (s x, s y, s, v) relative to the block origin,
+// in element order; its leaf index to ids and its sigma to bsig when those
+// are given.  Returns the number of records (block-uniform).
+__device__ int gather_round(const Tables& T, const Rect& r, ScanShared& sc, int e0, int n_e, float4* brec, int* ids,
+                            float* bsig, int wave, int lane)
 {
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const float lim = T.T2 * 1.001f;  // looser than any tile's test
     int total = 0;
-    for (int e0 = 0; e0 < n_el; e0 += 256 * UNROLL) {
-        int id[UNROLL], ii[UNROLL], jj[UNROLL], lv[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int e = e0 + u * 256 + (int)threadIdx.x;
-            id[u] = -1;
-            ii[u] = jj[u] = lv[u] = 0;
-            if (e < n_el) {
-                // the level owning e: the largest l with start[l] <= e (empty levels share
-                // their successor's start, so the largest such l owns elements)
-                int l = 0;
-#pragma unroll
-                for (int step = MAX_LEVELS / 2; step > 0; step >>= 1)
-                    if (sc.start[l + step] <= e) l += step;
-                const LevelWin& w = sc.lw[l];
-                const int local = e - w.start;
-                int q = (int)((float)local * w.inv_w);
-                int rem = local - q * w.wi;
-                if (rem < 0) { --q; rem += w.wi; }
-                if (rem >= w.wi) { ++q; rem -= w.wi; }
-                ii[u] = w.ia + rem;
-                jj[u] = w.ja + q;
-                lv[u] = l;
-                id[u] = T.node[w.off + (int64_t)jj[u] * w.S + ii[u]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            int v = id[u];
-            if (v >= 0) {
-                const LevelWin& w = sc.lw[lv[u]];
-                const double cx = T.x0 + (ii[u] + 0.5) * w.c, cy = T.y0 + (jj[u] + 0.5) * w.c;
-                const double dx = fmax(fmax(r.x0 - cx, cx - r.x1), 0.0);
-                const double dy = fmax(fmax(r.y0 - cy, cy - r.y1), 0.0);
-                if (!(dx * dx + dy * dy < w.R2) || v >= T.n) v = -1;
-            }
-            const uint64_t m = __ballot(v >= 0);
-            if (lane == 0) sc.wcnt[wave] = __popcll(m);
-            __syncthreads();
-            int base = total, all = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const int k = sc.wcnt[w];
-                base += w < wave ? k : 0;
-                all += k;
-            }
-            const int slot = base + __popcll(m & lt) - lo;
-            if (v >= 0 && slot >= 0 && slot < BCAP) bids[slot] = v;
-            total += all;
-            __syncthreads();
-        }
-    }
-    return total;
-}
-
-// Gathers the records of bids[0 .. nb) into brec as (s x, s y, s, v) relative
-// to the block origin (and sigma into bsig when given).
-__device__ inline void stage_block(const Tables& T, const Rect& r, const int* bids, int nb, float4* brec, float* bsig)
-{
 #pragma unroll
     for (int u = 0; u < BCAP / 256; ++u) {
-        const int c = u * 256 + (int)threadIdx.x;
-        if (c < nb) {
-            const int id = bids[c];
-            const float4 p = T.packed[id];
-            const float xr = (float)((double)p.x - r.x0), yr = (float)((double)p.y - r.y0);
-            brec[c] = make_float4(xr * p.w, yr * p.w, p.w, p.z);
-            if (bsig) bsig[c] = T.sigma[id];
+        const int eb = e0 + u * 256;
+        if (eb >= n_e) break;  // block-uniform
+        const int e = eb + (int)threadIdx.x;
+        bool keep = false;
+        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+        int p = 0;
+        if (e < n_e) {
+            int sg = 0;
+#pragma unroll
+            for (int step = RCAP / 2; step > 0; step >>= 1)
+                if (sc.seg_off[sg + step] <= e) sg += step;
+            p = sc.seg_pos[sg] + (e - sc.seg_off[sg]);
+            const float4 q = T.packed[p];
+            const double xr = (double)q.x - r.x0, yr = (double)q.y - r.y0;
+            const float dx = (float)fmax(fmax(-xr, xr - (r.x1 - r.x0)), 0.0) * q.w;
+            const float dy = (float)fmax(fmax(-yr, yr - (r.y1 - r.y0)), 0.0) * q.w;
+            keep = fmaf(dx, dx, dy * dy) < lim;
+            rec = make_float4((float)xr * q.w, (float)yr * q.w, q.w, q.z);
         }
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) sc.wcnt[u][wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const int k = sc.wcnt[u][w];
+            before += w < wave ? k : 0;
+            all += k;
+        }
+        if (keep) {
+            const int slot = total + before + __popcll(m & lt);
+            brec[slot] = rec;
+            if (ids) {
+                const int id = T.order[p];
+                ids[slot] = id;
+                if (bsig) bsig[slot] = T.sigma[id];
+            }
+        }
+        total += all;
     }
+    __syncthreads();
+    return total;
 }
 
 // True when record q (scaled) can reach the rectangle [x0, x1] x [y0, y1]
@@ -319,7 +340,6 @@ __device__ inline TileFrame tile_frame(const TexCascade& C, const Dom2& D, const
 
 struct DiscShared {
     float4 brec[BCAP];
-    int bids[BCAP];
     float4 trec_all[WAVES][TCAP];
     double rxl[BS + 1], rxr[BS + 1];
     uint32_t mbits[BS];
@@ -333,7 +353,6 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
                                                  float* __restrict__ tex, uint16_t* __restrict__ mask, DiscShared& sh)
 {
     float4* brec = sh.brec;
-    int* bids = sh.bids;
     int& any_vis = sh.any_vis;
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -356,12 +375,11 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     const float lim = T.T2 * 1.0001f, E = T.E;
     float4* trec = sh.trec_all[wave];
     float s0 = 0.0f, s1 = 0.0f;
-    const int n_el = block_levels(T, br, sh.scan);
-    for (int lo = 0;; lo += BCAP) {
-        const int total = block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
-        const int nb = min(total - lo, BCAP);
-        stage_block(T, br, bids, nb, brec, nullptr);
-        __syncthreads();
+    const int n_rows = block_rows(T, br, sh.scan);
+    for (int r0 = 0; r0 < n_rows; r0 += RCAP) {
+      const int n_e = chunk_rows(T, sh.scan, r0, n_rows, wave, lane);
+      for (int e0 = 0; e0 < n_e; e0 += BCAP) {
+        const int nb = gather_round(T, br, sh.scan, e0, n_e, brec, nullptr, nullptr, wave, lane);
         if (tile_vis) {
             int nt = 0;
             for (int c0 = 0; c0 < nb; c0 += 64) {
@@ -403,8 +421,8 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
             }
             wave_sync();
         }
-        if (lo + BCAP >= total) break;
-        __syncthreads();
+        __syncthreads();  // before the next round overwrites brec
+      }
     }
     if (!inside) return;
     float out = -INFINITY;
@@ -471,79 +489,78 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     unsigned short* tidx = sh.tidx_all[wave];
     // pass 1: S0 per texel (lanes own texels)
     float s0 = 0.0f;
-    int total = 0;
-    const int n_el = block_levels(T, br, sh.scan);
-    for (int lo = 0;; lo += BCAP) {
-        total = block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
-        const int nb = min(total - lo, BCAP);
-        stage_block(T, br, bids, nb, brec, bsig);
-        __syncthreads();
-        if (active) {
-            for (int c0 = 0; c0 < nb; c0 += 64) {
-                const int c = c0 + lane;
-                const float4 q0 = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-                const bool keep = c < nb && reaches(q0, f.x0, f.x1, f.y0, f.y1, lim);
-                uint64_t m = __ballot(keep);
-                while (m) {
-                    const int t = __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1;
-                    const float4 q = brec[c0 + t];
-                    const float dx = fmaf(f.npx, q.z, q.x), dy = fmaf(f.npy, q.z, q.y);
-                    s0 += fmaxf(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)) - E, 0.0f);
+    const int n_rows = block_rows(T, br, sh.scan);
+    int n_e = 0, nb = 0;
+    for (int r0 = 0; r0 < n_rows; r0 += RCAP) {
+        n_e = chunk_rows(T, sh.scan, r0, n_rows, wave, lane);
+        for (int e0 = 0; e0 < n_e; e0 += BCAP) {
+            nb = gather_round(T, br, sh.scan, e0, n_e, brec, bids, bsig, wave, lane);
+            if (active) {
+                for (int c0 = 0; c0 < nb; c0 += 64) {
+                    const int c = c0 + lane;
+                    const float4 q0 = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const bool keep = c < nb && reaches(q0, f.x0, f.x1, f.y0, f.y1, lim);
+                    uint64_t m = __ballot(keep);
+                    while (m) {
+                        const int t = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const float4 q = brec[c0 + t];
+                        s0 += rbf_weight(fmaf(f.npx, q.z, q.x), fmaf(f.npy, q.z, q.y), E);
+                    }
                 }
             }
+            __syncthreads();  // before the next round overwrites brec
         }
-        if (lo + BCAP >= total) break;
-        __syncthreads();
     }
     const float gn = act && s0 > 0.0f ? g / s0 : 0.0f;
     // pass 2: lanes own tile-list leaves; with a single round the block records are still staged
-    for (int lo = 0; lo < total; lo += BCAP) {
-        const int nb = min(total - lo, BCAP);
-        if (total > BCAP) {
-            __syncthreads();
-            block_scan(T, br, n_el, lo, bids, sh.scan, wave, lane);
-            stage_block(T, br, bids, nb, brec, bsig);
-            __syncthreads();
-        }
-        if (!active) continue;
-        int nt = 0;
-        for (int c0 = 0; c0 < nb; c0 += 64) {
-            const int c = c0 + lane;
-            const float4 q = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-            const bool keep = c < nb && reaches(q, f.x0, f.x1, f.y0, f.y1, lim);
-            const uint64_t m = __ballot(keep);
-            if (keep) tidx[nt + __popcll(m & lt)] = (unsigned short)c;
-            nt += __popcll(m);
-        }
-        wave_sync();
-        for (int c0 = 0; c0 < nt; c0 += 64) {
-            const int a = c0 + lane;
-            const bool own = a < nt;
-            const int c = own ? tidx[a] : 0;
-            const float4 q = own ? brec[c] : make_float4(1e18f, 1e18f, 0.f, 0.f);
-            const float sj = own ? bsig[c] : 1.0f;
-            float acc_v = 0.0f, acc_s = 0.0f;
-            uint64_t m = active;
-            while (m) {
-                const int t = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1;
-                const float tnx = __shfl(f.npx, t), tny = __shfl(f.npy, t), tg = __shfl(gn, t), tv = __shfl(vs, t);
-                const float dx = fmaf(tnx, q.z, q.x), dy = fmaf(tny, q.z, q.y);
-                const float r2 = fmaf(dx, dx, dy * dy);  // (s r)^2 = q^2 log2(e) / 2
-                const float ex = __builtin_amdgcn_exp2f(-r2);
-                const float w = ex - E;
-                if (w > 0.0f) {
-                    acc_v = fmaf(tg, w, acc_v);
-                    acc_s = fmaf(tg * (q.w - tv), ex * r2 * (2.0f / LOG2E) / sj, acc_s);
+    const bool single = n_rows <= RCAP && n_e <= BCAP;
+    for (int r0 = 0; r0 < n_rows; r0 += RCAP) {
+        if (!single) n_e = chunk_rows(T, sh.scan, r0, n_rows, wave, lane);
+        for (int e0 = 0; e0 < n_e; e0 += BCAP) {
+            if (!single) nb = gather_round(T, br, sh.scan, e0, n_e, brec, bids, bsig, wave, lane);
+            if (active) {
+                int nt = 0;
+                for (int c0 = 0; c0 < nb; c0 += 64) {
+                    const int c = c0 + lane;
+                    const float4 q = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const bool keep = c < nb && reaches(q, f.x0, f.x1, f.y0, f.y1, lim);
+                    const uint64_t m = __ballot(keep);
+                    if (keep) tidx[nt + __popcll(m & lt)] = (unsigned short)c;
+                    nt += __popcll(m);
                 }
+                wave_sync();
+                for (int c0 = 0; c0 < nt; c0 += 64) {
+                    const int a = c0 + lane;
+                    const bool own = a < nt;
+                    const int c = own ? tidx[a] : 0;
+                    const float4 q = own ? brec[c] : make_float4(1e18f, 1e18f, 0.f, 0.f);
+                    const float sj = own ? bsig[c] : 1.0f;
+                    float acc_v = 0.0f, acc_s = 0.0f;
+                    uint64_t m = active;
+                    while (m) {
+                        const int t = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const float tnx = __shfl(f.npx, t), tny = __shfl(f.npy, t), tg = __shfl(gn, t),
+                                    tv = __shfl(vs, t);
+                        const float dx = fmaf(tnx, q.z, q.x), dy = fmaf(tny, q.z, q.y);
+                        const float r2 = fmaf(dx, dx, dy * dy);  // (s r)^2 = q^2 log2(e) / 2
+                        const float ex = __builtin_amdgcn_exp2f(-r2);
+                        const float w = ex - E;
+                        if (w > 0.0f) {
+                            acc_v = fmaf(tg, w, acc_v);
+                            acc_s = fmaf(tg * (q.w - tv), ex * r2 * (2.0f / LOG2E) / sj, acc_s);
+                        }
+                    }
+                    if (own && (acc_v != 0.0f || acc_s != 0.0f)) {
+                        atomicAdd(&gv[bids[c]], acc_v);
+                        atomicAdd(&gs[bids[c]], acc_s);
+                    }
+                }
+                wave_sync();
             }
-            if (own && (acc_v != 0.0f || acc_s != 0.0f)) {
-                atomicAdd(&gv[bids[c]], acc_v);
-                atomicAdd(&gs[bids[c]], acc_s);
-            }
+            if (!single) __syncthreads();  // before the next round overwrites brec
         }
-        wave_sync();
     }
 }
 
@@ -611,13 +628,14 @@ hfr_status leaf_tables(const hfr_leaves* L, bool backward, Tables* out)
 {
     HFR_REQUIRE(L != nullptr, "leaves are NULL");
     HFR_REQUIRE(L->n >= 1 && L->n <= INT32_MAX, "leaf count %lld outside [1, INT32_MAX]", (long long)L->n);
-    HFR_REQUIRE(L->packed && L->level_radius && L->node, "packed records, level radii and node table are required");
+    HFR_REQUIRE(L->packed && L->level_radius && L->rank && L->order,
+                "packed records, level radii and the level index are required");
     HFR_REQUIRE(!backward || L->sigma, "sigma is required");
     HFR_REQUIRE(L->max_depth >= 0 && L->max_depth <= 15, "max_depth %d outside [0, 15]", L->max_depth);
     HFR_REQUIRE(std::isfinite(L->cutoff) && L->cutoff > 0, "cutoff must be positive");
     HFR_REQUIRE(std::isfinite(L->side) && L->side > 0 && std::isfinite(L->x0) && std::isfinite(L->y0),
                 "invalid lattice square");
-    *out = Tables{reinterpret_cast<const float4*>(L->packed), L->level_radius, L->node, L->sigma, (int)L->n,
+    *out = Tables{reinterpret_cast<const float4*>(L->packed), L->level_radius, L->rank, L->order, L->sigma, (int)L->n,
                   L->max_depth, L->x0, L->y0, L->side, 1.0 / L->side, std::exp(-0.5f * L->cutoff * L->cutoff),
                   0.5f * LOG2E * L->cutoff * L->cutoff};
     return HFR_OK;
@@ -628,8 +646,8 @@ extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
 {
     HFR_REQUIRE(L != nullptr, "leaves are NULL");
     HFR_REQUIRE(L->n >= 1 && L->n <= INT32_MAX, "leaf count %lld outside [1, INT32_MAX]", (long long)L->n);
-    HFR_REQUIRE(L->x && L->y && L->v && L->c && L->sigma && L->packed && L->level_radius,
-                "leaf arrays must not be NULL");
+    HFR_REQUIRE(L->x && L->y && L->v && L->c && L->sigma && L->packed && L->level_radius && L->order,
+                "leaf arrays and the level order must not be NULL");
     HFR_REQUIRE(L->max_depth >= 0 && L->max_depth <= 15, "max_depth %d outside [0, 15]", L->max_depth);
     HFR_REQUIRE(std::isfinite(L->cutoff) && L->cutoff > 0, "cutoff must be positive");
     HFR_REQUIRE(std::isfinite(L->side) && L->side > 0, "side must be positive");
@@ -638,7 +656,7 @@ extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
     HFR_LAUNCH_CHECK("pack_leaves (radius reset)");
     const int64_t blocks = std::min<int64_t>((L->n + 255) / 256, 2048);
     pack_leaves_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
-        L->x, L->y, L->v, L->c, L->sigma, L->cutoff, (float)L->side, L->max_depth,
+        L->x, L->y, L->v, L->c, L->sigma, L->order, L->cutoff, (float)L->side, L->max_depth,
         reinterpret_cast<float4*>(L->packed), L->level_radius, L->n);
     HFR_LAUNCH_CHECK("pack_leaves");
     return hfr_ok();

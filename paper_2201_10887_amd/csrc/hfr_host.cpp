@@ -342,16 +342,17 @@ extern "C" void hfr_neighbours_destroy(hfr_neighbours* nb) { delete nb; }
 
 // ------------------------------------------------------------ node table
 
-extern "C" hfr_status hfr_build_node_table(int64_t n, const float* x, const float* y, const float* c, double x0,
-                                           double y0, double side, int32_t max_depth, int32_t* node)
+extern "C" hfr_status hfr_build_level_index(int64_t n, const float* x, const float* y, const float* c, double x0,
+                                            double y0, double side, int32_t max_depth, int32_t* rank, int32_t* order)
 {
-    HFR_REQUIRE(node != nullptr, "node is NULL");
+    HFR_REQUIRE(rank != nullptr && order != nullptr, "rank and order must not be NULL");
     HFR_REQUIRE(max_depth >= 0 && max_depth <= 15, "max_depth %d outside [0, 15]", max_depth);
+    HFR_REQUIRE(n <= INT32_MAX, "leaf count %lld above INT32_MAX", (long long)n);
     LatticeLeaves lat;
     hfr_status st = lattice_of(n, x, y, c, x0, y0, side, max_depth, lat);
     if (st != HFR_OK) return st;
-    const int64_t total = ((int64_t(1) << (2 * (max_depth + 1))) - 1) / 3;
-    std::fill(node, node + total, -1);
+    const int64_t total = ((int64_t(1) << (2 * (max_depth + 1))) - 1) / 3 + max_depth + 1;
+    std::fill(rank, rank + total, 0);
     // coverage count on the finest lattice detects gaps and overlaps
     const int64_t S = int64_t(1) << max_depth;
     std::vector<uint8_t> cover;
@@ -360,12 +361,12 @@ extern "C" hfr_status hfr_build_node_table(int64_t n, const float* x, const floa
     } catch (const std::bad_alloc&) {
         return hfr_fail(HFR_ENOMEM, "out of host memory");
     }
+    auto level_off = [](int l) { return ((int64_t(1) << (2 * l)) - 1) / 3 + l; };
     for (int64_t a = 0; a < n; ++a) {
         const int l = lat.level[a];
-        const int64_t off = ((int64_t(1) << (2 * l)) - 1) / 3;
-        int32_t& slot = node[off + ((int64_t)lat.j[a] << l) + lat.i[a]];
-        HFR_REQUIRE(slot < 0, "leaves %d and %lld share a lattice node", slot, (long long)a);
-        slot = (int32_t)a;
+        int32_t& cnt = rank[level_off(l) + ((int64_t)lat.j[a] << l) + lat.i[a] + 1];
+        HFR_REQUIRE(cnt == 0, "leaf %lld shares its lattice node with another leaf", (long long)a);
+        cnt = 1;
         const int sh = max_depth - l;
         const int64_t i0 = (int64_t)lat.i[a] << sh, j0 = (int64_t)lat.j[a] << sh, w = int64_t(1) << sh;
         for (int64_t jj = j0; jj < j0 + w; ++jj)
@@ -375,6 +376,21 @@ extern "C" hfr_status hfr_build_node_table(int64_t n, const float* x, const floa
             }
     }
     for (int64_t a = 0; a < S * S; ++a) HFR_REQUIRE(cover[a], "lattice cell %lld is not covered", (long long)a);
+    // exclusive prefix counts, level after level: rank[off_l + q] = leaves before (l, q)
+    int64_t acc = 0;
+    for (int l = 0; l <= max_depth; ++l) {
+        int32_t* r = rank + level_off(l);
+        const int64_t cells = int64_t(1) << (2 * l);
+        r[0] = (int32_t)acc;
+        for (int64_t q = 1; q <= cells; ++q) {
+            acc += r[q];
+            r[q] = (int32_t)acc;
+        }
+    }
+    for (int64_t a = 0; a < n; ++a) {
+        const int l = lat.level[a];
+        order[rank[level_off(l) + ((int64_t)lat.j[a] << l) + lat.i[a]]] = (int32_t)a;
+    }
     return hfr_ok();
 }
 

@@ -1,7 +1,7 @@
 """Frame-level orchestration of the per-frame path on one GPU.
 
-``Renderer`` owns the device-resident heightfield (leaves, dense node
-table, per-level truncation radii) and the per-frame buffers (cascade textures,
+``Renderer`` owns the device-resident heightfield (leaves, level
+index, per-level truncation radii) and the per-frame buffers (cascade textures,
 visibility bits, max-mipmaps), all allocated once; ``forward`` runs cascade
 fitting (host), discretize, max-mipmap and ray casting (device) on the
 current stream and allocates nothing.  ``RenderDepth`` is the
@@ -24,8 +24,8 @@ class Renderer:
         self.K, self.N, self.lam, self.overlap = int(cascades), int(tex_n), float(split_lambda), float(overlap)
         self.c_min = float(np.min(leaves["c"]))
         self.dom = api.domain(_Dom(x0, y0, x0 + side, y0 + side, float(np.min(leaves["v"])), float(np.max(leaves["v"]))))
-        node = api.build_node_table(leaves, side, max_depth, x0, y0)
-        self.L = api.DeviceLeaves(leaves, node, side, max_depth, cutoff, x0, y0, device=device)
+        index = api.build_level_index(leaves, side, max_depth, x0, y0)
+        self.L = api.DeviceLeaves(leaves, index, side, max_depth, cutoff, x0, y0, device=device)
         api.pack_leaves(self.L)
         K, N = self.K, self.N
         self.tex = torch.empty((K, N, N), dtype=torch.float32, device=device)

@@ -20,8 +20,8 @@ from oracle import raycast as oray
 def device_leaves(scene):
     from paper_2201_10887_amd import api
     w = scene.work
-    node = api.build_node_table(scene.leaves, w.side, w.max_depth)
-    L = api.DeviceLeaves(scene.leaves, node, w.side, w.max_depth, w.cutoff)
+    index = api.build_level_index(scene.leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(scene.leaves, index, w.side, w.max_depth, w.cutoff)
     api.pack_leaves(L)
     return L
 

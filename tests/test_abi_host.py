@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 3
+    assert api.abi_version() == 4
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -71,26 +71,49 @@ def test_neighbours_and_locator_c1(tiny_scene):
 
 
 @pytest.mark.parametrize("seed,depth,p", [(1, 5, 0.6), (2, 6, 0.45), (3, 0, 0.5)])
-def test_node_table(seed, depth, p):
+def test_level_index(seed, depth, p):
+    """Sorted order and per-level prefix counts, written out from their definition."""
     struct = synth.random_leaf_structure(depth, p, seed)
     n = len(struct)
     L = synth.leaves_from_structure(struct, 640.0, np.zeros(n), np.ones(n))
-    node = api.build_node_table(L, 640.0, depth)
-    assert len(node) == (4 ** (depth + 1) - 1) // 3
-    want = np.full(len(node), -1, np.int64)
-    for a, (l, i, j) in enumerate(struct):
-        want[(4 ** l - 1) // 3 + j * 2 ** l + i] = a
-    assert np.array_equal(node, want)
+    rank, order = api.build_level_index(L, 640.0, depth)
+    assert len(rank) == (4 ** (depth + 1) - 1) // 3 + depth + 1 and len(order) == n
+    key = sorted(range(n), key=lambda a: (struct[a][0], struct[a][2], struct[a][1]))
+    assert list(order) == key
+    want = []
+    for l in range(depth + 1):
+        S = 2 ** l
+        for q in range(S * S + 1):  # leaves of coarser levels, plus level-l leaves before node q
+            want.append(sum(1 for (lv, i, j) in struct if lv < l or (lv == l and j * S + i < q)))
+    assert np.array_equal(rank, want)
 
 
-def test_node_table_rejects_gaps_and_overlaps():
+def test_level_index_row_ranges_find_every_leaf():
+    """Every leaf is the one leaf of its own node's unit range, empty nodes have empty ranges."""
+    struct = synth.random_leaf_structure(6, 0.5, 9)
+    n = len(struct)
+    L = synth.leaves_from_structure(struct, 64.0, np.zeros(n), np.ones(n))
+    rank, order = api.build_level_index(L, 64.0, 6)
+    at = {(l, i, j): a for a, (l, i, j) in enumerate(struct)}
+    for l in range(7):
+        S, off = 2 ** l, api.rank_offset(l)
+        for j in range(S):
+            for i in range(S):
+                q = off + j * S + i
+                if (l, i, j) in at:
+                    assert rank[q + 1] - rank[q] == 1 and order[rank[q]] == at[(l, i, j)]
+                else:
+                    assert rank[q + 1] == rank[q]
+
+
+def test_level_index_rejects_gaps_and_overlaps():
     struct = synth.random_leaf_structure(3, 0.7, 5)
     L = synth.leaves_from_structure(struct[1:], 64.0, np.zeros(len(struct) - 1), np.ones(len(struct) - 1))
     with pytest.raises(_lib.HfrError, match="HFR_EINVAL"):
-        api.build_node_table(L, 64.0, 3)
+        api.build_level_index(L, 64.0, 3)
     L2 = synth.leaves_from_structure(struct + [(0, 0, 0)], 64.0, np.zeros(len(struct) + 1), np.ones(len(struct) + 1))
     with pytest.raises(_lib.HfrError, match="HFR_EINVAL"):
-        api.build_node_table(L2, 64.0, 3)
+        api.build_level_index(L2, 64.0, 3)
 
 
 def _compare_cascades(a, b, scale):
@@ -175,13 +198,16 @@ def test_invalid_arguments_rejected_before_launch():
     # empty domain
     empty = api.domain(synth.Domain(0, 0, 0, 100, 0, 10))
     _raise_einval("hfr_raycast", ctypes.byref(cam), ctypes.byref(empty), cs, 2, dummy, dummy, dummy, dummy, None)
-    # discretize: missing node table, bad cutoff, bad depth
-    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, 4, 3.5, 0.0, 0.0, 1.0)
+    # discretize: missing level index, bad cutoff, bad depth
+    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, dummy, 4, 3.5, 0.0, 0.0, 1.0)
     _raise_einval("hfr_discretize", ctypes.byref(L), ctypes.byref(dom), cs, 2, dummy, None, None)
-    L2 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, -1.0, 0.0, 0.0, 1.0)
+    _raise_einval("hfr_discretize", ctypes.byref(api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy,
+                                                             dummy, None, 4, 3.5, 0.0, 0.0, 1.0)),
+                  ctypes.byref(dom), cs, 2, dummy, None, None)
+    L2 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, -1.0, 0.0, 0.0, 1.0)
     _raise_einval("hfr_discretize", ctypes.byref(L2), ctypes.byref(dom), cs, 2, dummy, None, None)
     _raise_einval("hfr_pack_leaves", ctypes.byref(L2), None)
-    L3 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 16, 3.5, 0.0, 0.0, 1.0)
+    L3 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 16, 3.5, 0.0, 0.0, 1.0)
     _raise_einval("hfr_discretize_backward", ctypes.byref(L3), ctypes.byref(dom), cs, 2, dummy, dummy, dummy,
                   dummy, None)
     _raise_einval("hfr_pack_leaves", ctypes.byref(api.Leaves()), None)
@@ -196,7 +222,7 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 3
+    assert lib.hfr_abi_version() == 4
 
 
 def test_batch_arguments_rejected_before_any_device_call():
@@ -204,7 +230,7 @@ def test_batch_arguments_rejected_before_any_device_call():
     lib = _lib.load()
     dummy = 0x1000
     dom = api.domain(synth.Domain(0, 0, 100, 100, 0, 10))
-    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 3.5, 0.0, 0.0, 100.0)
+    L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 3.5, 0.0, 0.0, 100.0)
     fields = (_lib.BatchField * 1)()
     fields[0].leaves, fields[0].dom = L, dom
 
@@ -225,8 +251,8 @@ def test_batch_arguments_rejected_before_any_device_call():
     _raise_einval("hfr_batch_plan_create", fields, 1, view(c_min=0.0), 1, ctypes.byref(h))
     _raise_einval("hfr_batch_plan_create", fields, 1, view(split_lambda=1.5), 1, ctypes.byref(h))
     bad = (_lib.BatchField * 1)()
-    bad[0].leaves, bad[0].dom = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, 4, 3.5,
-                                           0.0, 0.0, 100.0), dom
+    bad[0].leaves, bad[0].dom = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, None, 4,
+                                           3.5, 0.0, 0.0, 100.0), dom
     _raise_einval("hfr_batch_plan_create", bad, 1, view(), 1, ctypes.byref(h))
     assert h.value is None
     t = _lib.BatchTuning(4, 4, 12, 4)

@@ -38,15 +38,15 @@ def large(gpu):
     dem = synth.fbm_dem(w.dem_n, w.octaves, w.hurst, w.seed, mountains=w.mountains, device="cuda")
     _say("raster done; oracle quadtree")
     leaves = oqt.build_quadtree(dem, w.side, w.max_depth, w.tau)
-    _say(f"{len(leaves['x'])} leaves; cascades, node table, visibility")
+    _say(f"{len(leaves['x'])} leaves; cascades, level index, visibility")
     leaves["sigma"] = np.full(len(leaves["x"]), w.sigma, np.float32)
     dom = synth.Domain(0.0, 0.0, w.side, w.side, float(leaves["v"].min()), float(leaves["v"].max()))
     cam = synth.camera_of(w, dem)
     cs = ocas.fit_cascades(cam, dom, w.cascades, w.tex_n, w.split_lambda, w.overlap, float(leaves["c"].min()))
-    node = api.build_node_table(leaves, w.side, w.max_depth)
-    L = api.DeviceLeaves(leaves, node, w.side, w.max_depth, w.cutoff)
+    index = api.build_level_index(leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(leaves, index, w.side, w.max_depth, w.cutoff)
     api.pack_leaves(L)
-    del node
+    del index
     vis = [odisc.visibility(c) for c in cs]  # every texel of every cascade
     _say("scene ready")
     return dict(w=w, dem=dem, leaves=leaves, dom=dom, cam=cam, cs=cs, L=L, cas=api.cascades_from(cs), vis=vis)

@@ -33,8 +33,8 @@ def medium(gpu):
     dom = synth.Domain(0.0, 0.0, w.side, w.side, float(leaves["v"].min()), float(leaves["v"].max()))
     cam = synth.camera_of(w, dem)
     cs = ocas.fit_cascades(cam, dom, w.cascades, w.tex_n, w.split_lambda, w.overlap, float(leaves["c"].min()))
-    node = api.build_node_table(leaves, w.side, w.max_depth)
-    L = api.DeviceLeaves(leaves, node, w.side, w.max_depth, w.cutoff)
+    index = api.build_level_index(leaves, w.side, w.max_depth)
+    L = api.DeviceLeaves(leaves, index, w.side, w.max_depth, w.cutoff)
     api.pack_leaves(L)
     return dict(w=w, dem=dem, leaves=leaves, dom=dom, cam=cam, cs=cs, L=L, cas=api.cascades_from(cs))
 
