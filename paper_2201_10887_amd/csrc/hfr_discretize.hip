@@ -160,43 +160,49 @@ struct ScanShared {
     int wcnt[2][WAVES];          // per-wave counts (two buffers: consecutive prefixes need no barrier between)
 };
 
-// Windows of every level around the block rectangle (thread l fills level l):
-// the lattice nodes within the level's largest truncation radius of the
-// rectangle, widened by one node on each side.  Returns the number of window
-// rows over all levels (block-uniform).
-__device__ int block_rows(const Tables& T, const Rect& r, ScanShared& sc)
+// Largest truncation radius of level threadIdx.x (0 for other threads); loaded
+// when a block starts so that its latency hides behind the visibility test.
+__device__ inline float level_radius(const Tables& T)
+{
+    return (int)threadIdx.x <= T.max_depth ? T.radius[threadIdx.x] : 0.0f;
+}
+
+// Windows of every level around the block rectangle (lane l of wave 0 fills
+// level l from its radius Rf): the lattice nodes within the level's largest
+// truncation radius of the rectangle, widened by one node on each side.
+// Returns the number of window rows over all levels (block-uniform).
+__device__ int block_rows(const Tables& T, const Rect& r, float Rf, ScanShared& sc)
 {
     const int t = threadIdx.x;
-    if (t <= T.max_depth) {
+    if (t < 64) {
         const int l = t;
-        LevelWin w{};
         int rows = 0;
-        const float Rf = T.radius[l];
-        if (Rf > 0.0f) {
-            const double R = Rf;
-            const double inv_c = ldexp(T.inv_side, l);
-            const int S = 1 << l;
-            const int ia = max(0, (int)floor((r.x0 - R - T.x0) * inv_c - 0.5) - 1);
-            const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) * inv_c - 0.5) + 1);
-            const int ja = max(0, (int)floor((r.y0 - R - T.y0) * inv_c - 0.5) - 1);
-            const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) * inv_c - 0.5) + 1);
-            if (ib >= ia && jb >= ja) {
-                rows = jb - ja + 1;
-                w = LevelWin{((int64_t(1) << (2 * l)) - 1) / 3 + l, ia, ib, ja, S};
+        if (l <= T.max_depth) {
+            LevelWin w{};
+            if (Rf > 0.0f) {
+                const double R = Rf;
+                const double inv_c = ldexp(T.inv_side, l);
+                const int S = 1 << l;
+                const int ia = max(0, (int)floor((r.x0 - R - T.x0) * inv_c - 0.5) - 1);
+                const int ib = min(S - 1, (int)ceil((r.x1 + R - T.x0) * inv_c - 0.5) + 1);
+                const int ja = max(0, (int)floor((r.y0 - R - T.y0) * inv_c - 0.5) - 1);
+                const int jb = min(S - 1, (int)ceil((r.y1 + R - T.y0) * inv_c - 0.5) + 1);
+                if (ib >= ia && jb >= ja) {
+                    rows = jb - ja + 1;
+                    w = LevelWin{((int64_t(1) << (2 * l)) - 1) / 3 + l, ia, ib, ja, S};
+                }
             }
+            sc.lw[l] = w;
         }
-        sc.lw[l] = w;
-        sc.rstart[l + 1] = rows;
-    }
-    __syncthreads();
-    if (t == 0) {
-        int acc = 0;
-        for (int l = 0; l <= T.max_depth; ++l) {
-            const int rows = sc.rstart[l + 1];
-            sc.rstart[l] = acc;
-            acc += rows;
+        // rstart[l + 1] = rows of levels 0 .. l (levels past max_depth add none)
+        int incl = rows;
+#pragma unroll
+        for (int o = 1; o < MAX_LEVELS; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (l >= o) incl += y;
         }
-        for (int l = T.max_depth + 1; l <= MAX_LEVELS; ++l) sc.rstart[l] = acc;
+        if (l < MAX_LEVELS) sc.rstart[l + 1] = incl;
+        if (l == 0) sc.rstart[0] = 0;
     }
     __syncthreads();
     return sc.rstart[MAX_LEVELS];
@@ -205,9 +211,10 @@ __device__ int block_rows(const Tables& T, const Rect& r, ScanShared& sc)
 // Window rows [r0, r0 + RCAP): lane t reads the sorted-position range of row
 // r0 + t from the rank table; seg_off becomes the exclusive prefix of the
 // row lengths.  Returns the chunk's element count (block-uniform).
+// The previous chunk's rows were last read inside gather_round or before this
+// function's own closing barrier, so they may be overwritten without one.
 __device__ int chunk_rows(const Tables& T, ScanShared& sc, int r0, int n_rows, int wave, int lane)
 {
-    __syncthreads();  // nobody reads the previous chunk's rows any more
     const int r = r0 + (int)threadIdx.x;
     int pos = 0, len = 0;
     if (r < n_rows) {
@@ -360,6 +367,7 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
     const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
     const bool inside = i < N && j < N;
+    const float Rf = level_radius(T);
     if (threadIdx.x == 0) any_vis = 0;
     const bool vis = block_visibility(C, bi0, bj0, i, j, sh.rxl, sh.rxr, sh.mbits, mask);
     if (vis) any_vis = 1;
@@ -375,7 +383,7 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     const float lim = T.T2 * 1.0001f, E = T.E;
     float4* trec = sh.trec_all[wave];
     float s0 = 0.0f, s1 = 0.0f;
-    const int n_rows = block_rows(T, br, sh.scan);
+    const int n_rows = block_rows(T, br, Rf, sh.scan);
     for (int r0 = 0; r0 < n_rows; r0 += RCAP) {
       const int n_e = chunk_rows(T, sh.scan, r0, n_rows, wave, lane);
       for (int e0 = 0; e0 < n_e; e0 += BCAP) {
@@ -470,6 +478,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
     const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
     const bool inside = i < N && j < N;
+    const float Rf = level_radius(T);
     float g = 0.0f, vs = 0.0f;
     if (inside) {
         g = gtex[(int64_t)j * N + i];
@@ -489,7 +498,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     unsigned short* tidx = sh.tidx_all[wave];
     // pass 1: S0 per texel (lanes own texels)
     float s0 = 0.0f;
-    const int n_rows = block_rows(T, br, sh.scan);
+    const int n_rows = block_rows(T, br, Rf, sh.scan);
     int n_e = 0, nb = 0;
     for (int r0 = 0; r0 < n_rows; r0 += RCAP) {
         n_e = chunk_rows(T, sh.scan, r0, n_rows, wave, lane);
