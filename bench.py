@@ -271,13 +271,14 @@ def batch_main(args):
     ms["graph_fwd_bwd"] = timed(g_train.replay, args.steps, stream)
 
     cas = [R.cascades(v) for v in range(R.n_views)]
+    works = [api.ray_workspace(cams[v], "cuda") for v in range(R.n_views)]
 
     def per_view_fwd():
         for v, b in enumerate(R.bufs):
             f = R.fields[R.specs[v].field]
             api.discretize(f.L, f.dom, cas[v], b["tex"])
             api.build_maxmip(b["tex"], b["mip"])
-            api.raycast(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["depth"], b["hit"])
+            api.raycast(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["depth"], b["hit"], None, works[v])
 
     def per_view_train():
         for f in R.fields:
@@ -287,9 +288,10 @@ def batch_main(args):
             f = R.fields[R.specs[v].field]
             api.discretize(f.L, f.dom, cas[v], b["tex"])
             api.build_maxmip(b["tex"], b["mip"])
-            api.raycast(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["depth"], b["hit"])
+            api.raycast(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["depth"], b["hit"], None, works[v])
             b["grad_tex"].zero_()
-            api.raycast_backward(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["grad_depth"], b["grad_tex"])
+            api.raycast_backward(cams[v], f.dom, cas[v], b["tex"], b["mip"], b["grad_depth"], b["grad_tex"], None,
+                                 works[v])
             api.discretize_backward(f.L, f.dom, cas[v], b["tex"], b["grad_tex"], f.grad_v, f.grad_sigma)
 
     per_view_train()
@@ -363,6 +365,9 @@ def main():
     def forward():
         return R.forward(cam, None, depth, hit)
 
+    tuned = R.tune_raycast(cam)
+    print(f"[bench] long-ray queue: forward {R.long_ray_queue}, adjoint {R.long_ray_queue_backward} {tuned}",
+          file=sys.stderr, flush=True)
     _, _, cas = forward()
     torch.cuda.synchronize()
     gen = torch.Generator(device="cuda").manual_seed(1003)
@@ -387,8 +392,9 @@ def main():
     stage = {
         "discretize": lambda: api.discretize(R.L, R.dom, cas, R.tex, R.mask),
         "build_maxmip": lambda: api.build_maxmip(R.tex, R.mip),
-        "raycast": lambda: api.raycast(cam, R.dom, cas, R.tex, R.mip, depth, hit),
-        "raycast_backward": lambda: api.raycast_backward(cam, R.dom, cas, R.tex, R.mip, grad_depth, gtex),
+        "raycast": lambda: api.raycast(cam, R.dom, cas, R.tex, R.mip, depth, hit, None, R.ray_work(cam)),
+        "raycast_backward": lambda: api.raycast_backward(cam, R.dom, cas, R.tex, R.mip, grad_depth, gtex, None,
+                                                         R.ray_work(cam, backward=True)),
         "discretize_backward": lambda: api.discretize_backward(R.L, R.dom, cas, R.tex, gtex, gv, gs),
     }
     stage_ms = {k: timed(f, args.steps, stream) for k, f in stage.items()}
@@ -441,6 +447,7 @@ def main():
         "fwd_bwd_ms": round(ms_train, 4),
         "fwd_bwd_over_fwd": round(ms_train / ms_fwd, 3),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "long_ray_queue": {"forward": R.long_ray_queue, "adjoint": R.long_ray_queue_backward, "tuning_ms": tuned},
         "fit_cascades_host_us": round(fit_us, 1),
         "gtexel_per_s": round(vis_texels / (stage_ms["discretize"] * 1e-3) / 1e9, 3),
         "gtexel_per_s_all": round(K * R.N * R.N / (stage_ms["discretize"] * 1e-3) / 1e9, 3),

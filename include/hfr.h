@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 4
+#define HFR_ABI_VERSION 5
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -249,10 +249,19 @@ hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, float* mip, 
  * a = clamp((d(t_A) - split) / (far - split), 0, 1) of the nearer cascade.
  * depth: device float[H][W], +inf on a miss.  hit: device int32[H][W],
  * (k << 26) | (j << 13) | i of hit A's cell, -1 on a miss.  Geometry is
- * FP64 throughout.  EINVAL: image size outside [1, 16384], K/N as above. */
+ * FP64 throughout.
+ * work: device int32[W H + 2] scratch (its contents on entry do not matter;
+ * the call overwrites them), or NULL.  With it, a ray still walking after a
+ * fixed number of cell steps is queued there and finished by a second
+ * kernel in which several lanes share it, each walking one consecutive piece
+ * of its parameter range (the first hit is that of the earliest piece with
+ * one): the few long rays that graze the surface near the horizon stop
+ * setting the frame time.  Results agree with the NULL path up to FP64
+ * rounding of the hit parameter.  Concurrent calls must not share work.
+ * EINVAL: image size outside [1, 16384], K/N as above. */
 hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
                        int32_t K, const float* tex, const float* mip, float* depth, int32_t* hit,
-                       hfr_stream stream);
+                       int32_t* work, hfr_stream stream);
 
 /* Adjoint of hfr_raycast: recomputes every ray (nothing is stored by the
  * forward pass) and ACCUMULATES into the caller-zeroed grad_tex
@@ -260,11 +269,12 @@ hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_c
  * respect to the texel heights: dt/dh_c = phi_c(u, v) / f'(t) at a patch
  * root (implicit function theorem on z(t) - B(u(t), v(t)) = 0), chained
  * through the overlap blend; zero for hits at the start of a cascade
- * segment.  grad_depth: device float[H][W] (ignored where the ray misses). */
+ * segment.  grad_depth: device float[H][W] (ignored where the ray misses).
+ * work: as for hfr_raycast. */
 hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom,
                                 const hfr_cascade* cas, int32_t K, const float* tex,
                                 const float* mip, const float* grad_depth, float* grad_tex,
-                                hfr_stream stream);
+                                int32_t* work, hfr_stream stream);
 
 /* Adjoint of hfr_discretize (Eq. 2 and Eq. 1): ACCUMULATES into the
  * caller-zeroed grad_v and grad_sigma (device float[n])
@@ -289,8 +299,9 @@ hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
  * workgroups take work from per-XCD queues and steal from other queues when
  * theirs is empty, so views of uneven size share the GPU without a launch
  * per view.  The per-view work is the same as hfr_discretize,
- * hfr_build_maxmip and hfr_raycast (bit-identical outputs) and their
- * adjoints; the batch is not in the paper, which renders one view per frame.
+ * hfr_build_maxmip and hfr_raycast without a long-ray queue (work = NULL;
+ * bit-identical outputs) and their adjoints; the batch is not in the paper,
+ * which renders one view per frame.
  *
  * The plan is a library-owned host object holding device copies of the
  * field and view descriptors (allocated by hfr_batch_plan_create, the only

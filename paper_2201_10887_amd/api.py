@@ -237,7 +237,23 @@ def build_maxmip(tex, mip=None, stream=None):
     return mip
 
 
-def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, stream=None):
+def ray_workspace(cam, device) -> "torch.Tensor":
+    """Scratch for the long-ray queue of ``raycast`` / ``raycast_backward`` (int32[W H + 2])."""
+    import torch
+    return torch.empty(cam.width * cam.height + 2, dtype=torch.int32, device=device)
+
+
+def _work_ptr(work, cam, device):
+    """``work``: a workspace tensor, True (allocate one) or None / False (no long-ray queue)."""
+    import torch
+    if work is None or work is False:
+        return None
+    if work is True:
+        work = ray_workspace(cam, device)
+    return _dev(work, torch.int32, (cam.width * cam.height + 2,), "work")
+
+
+def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, stream=None, work=True):
     import torch
     K, N = len(cascades), cascades[0].n
     if depth is None:
@@ -247,11 +263,12 @@ def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, st
     call("hfr_raycast", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
          _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
          _dev(depth, torch.float32, (cam.height, cam.width), "depth"),
-         _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _stream(stream))
+         _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _work_ptr(work, cam, tex.device), _stream(stream))
     return depth, hit
 
 
-def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, grad_tex=None, stream=None):
+def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, grad_tex=None, stream=None,
+                     work=True):
     import torch
     K, N = len(cascades), cascades[0].n
     if grad_tex is None:
@@ -259,7 +276,7 @@ def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, gra
     call("hfr_raycast_backward", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
          _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
          _dev(grad_depth, torch.float32, (cam.height, cam.width), "grad_depth"),
-         _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _stream(stream))
+         _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _work_ptr(work, cam, tex.device), _stream(stream))
     return grad_tex
 
 

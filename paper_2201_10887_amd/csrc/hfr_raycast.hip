@@ -13,11 +13,21 @@
 // climbs at most one level, and not at all after a cell whose patch it had to
 // test: the frame time is set by the longest rays, which graze the surface
 // and gain nothing from larger nodes.
+//
+// Long rays.  Those few rays come in clusters (whole waves just below the
+// horizon) and spend their steps walking node after node a little above the
+// surface.  The frame kernel gives every ray a budget of RAY_BUDGET steps;
+// rays that exhaust it go to a queue in the caller's workspace, and a second,
+// persistent kernel walks each queued ray with RAY_SPLIT lanes, which test
+// the next RAY_SPLIT nodes of the current level along the ray at once.
+#include <climits>
+
 #include "hfr_device.h"
 
 namespace {
 
-
+constexpr int RAY_BUDGET = 64;  // cell-walk steps a pixel may take in the frame kernel
+constexpr int RAY_SPLIT = 16;   // lanes that share one queued ray
 
 struct Ray {
     double o[3], d[3], inv_d[2];
@@ -154,34 +164,190 @@ __device__ inline double node_exit(const Ray& r, const RayCas& c, int ci, int cj
     return te;
 }
 
-__device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __restrict__ tex,
-                          const float* __restrict__ mip, double ta, double tb, Hit& h)
+// Root of the bilinear patch of cell (ci, cj) (texels t00 .. t11) along the
+// ray piece [t, te] whose start height is za: true with the hit in h.
+__device__ inline bool patch_hit(const Ray& r, const RayCas& c, int k, int ci, int cj, double t, double te, double za,
+                                 double ta, float t00, float t10, float t01, float t11, Hit& h)
 {
-    if (!(ta < tb)) return false;
+    const double h00 = t00, h10 = t10, h01 = t01, h11 = t11;
+    const double u0 = ((r.o[0] + t * r.d[0]) - c.x0) * c.inv_hx - ci;
+    const double v0 = ((r.o[1] + t * r.d[1]) - c.y0) * c.inv_hy - cj;
+    const double du = r.d[0] * c.inv_hx, dv = r.d[1] * c.inv_hy;
+    const double A = h10 - h00, B = h01 - h00, C = (h00 - h10) - (h01 - h11);
+    const double cc = za - (h00 + A * u0 + B * v0 + C * u0 * v0);
+    const double bb = r.d[2] - A * du - B * dv - C * (u0 * dv + v0 * du);
+    const double aa = -C * du * dv;
+    double tau = 0.0;
+    if (!(cc <= 0.0 || smallest_root(aa, bb, cc, te - t, tau))) return false;
+    h.k = k;
+    h.i = ci;
+    h.j = cj;
+    h.t = t + tau;
+    h.u = u0 + tau * du;
+    h.v = v0 + tau * dv;
+    h.fp = 2.0 * aa * tau + bb;
+    h.start = (cc <= 0.0 && t == ta);
+    return true;
+}
+
+// The cell's four texels and its maximum (-inf when one is invisible).
+__device__ inline float cell_texels(const float* __restrict__ tex, int N, int ci, int cj, float& t00, float& t10,
+                                    float& t01, float& t11)
+{
+    const int64_t b = (int64_t)cj * N + ci;
+    t00 = tex[b];
+    t10 = tex[b + 1];
+    t01 = tex[b + N];
+    t11 = tex[b + N + 1];
+    return (isfinite(t00) && isfinite(t10) && isfinite(t01) && isfinite(t11))
+               ? fmaxf(fmaxf(t00, t10), fmaxf(t01, t11)) : -INFINITY;
+}
+
+// First root of the ray in [ta, tb] of cascade k: 1 with the hit in h, 0 when
+// there is none, -1 when the step budget runs out first.  G > 1: the G lanes
+// of an aligned group hold the same ray and call this together, and every
+// step tests the next G nodes of the current level along the ray at once
+// (lane s the s-th: entered after the s-th crossing of the merged x- and
+// y-boundary sequences, found by a co-rank search, with the boundary
+// arithmetic of node_exit).  The walk descends into the first node the ray
+// reaches below the maximum of, skips all G when it passes above them, and at
+// level 0 keeps the earliest cell that holds a root.
+template <int G>
+__device__ int first_hit(const Ray& r, const RayCas& c, int k, const float* __restrict__ tex,
+                         const float* __restrict__ mip, double ta, double tb, Hit& h, int& budget, int s)
+{
+    if (!(ta < tb)) return 0;
     const int N = c.n, L = c.levels;
     double t = ta;
     double t1 = piece_end(r, c, t, tb);
     int ci, cj;
     cell_at(r, c, 0.5 * (t + t1), ci, cj);
     int l = L;
+    bool probe = true;  // G > 1: the first step looks down through the levels at ta
     // every iteration either descends a level or moves to a later piece
     const int max_iter = 8 * N * (L + 2) + 64;
     for (int it = 0; it < max_iter; ++it) {
+        if (--budget < 0) return -1;
+        if constexpr (G > 1) {
+            // A probe tests the node holding t on levels l, l - 1, ..., lane s level l - s; a
+            // march tests the next G nodes of level l along the ray, lane s the s-th: entered
+            // after a crossings of the level's x-boundaries and b of its y-boundaries, a + b = s.
+            int ls = l, qx, qy;
+            double p0, p1;
+            bool valid;
+            if (probe) {
+                ls = l - s;
+                valid = ls >= 0;
+                ls = max(ls, 0);
+                qx = ci >> ls;
+                qy = cj >> ls;
+                p0 = t;
+                p1 = fmax(node_exit(r, c, ci, cj, ls, tb), t1);
+            } else {
+                const int nx = ci >> l, ny = cj >> l;
+                auto TX = [&](int a) {
+                    return r.d[0] == 0.0
+                               ? INFINITY
+                               : (lattice_pos(c.x0, (r.d[0] > 0.0 ? nx + 1 + a : nx - a) << l, c.hx) - r.o[0]) *
+                                     r.inv_d[0];
+                };
+                auto TY = [&](int b) {
+                    return r.d[1] == 0.0
+                               ? INFINITY
+                               : (lattice_pos(c.y0, (r.d[1] > 0.0 ? ny + 1 + b : ny - b) << l, c.hy) - r.o[1]) *
+                                     r.inv_d[1];
+                };
+                int lo = 0, hi = s;
+                while (lo < hi) {  // smallest a whose next x-crossing comes after the (s - a)-th y-crossing
+                    const int mid = (lo + hi) >> 1;
+                    if (TX(mid) <= TY(s - mid - 1)) lo = mid + 1;
+                    else hi = mid;
+                }
+                const int a = lo, b = s - a;
+                p0 = s == 0 ? t : fmax(a > 0 ? TX(a - 1) : -INFINITY, b > 0 ? TY(b - 1) : -INFINITY);
+                p1 = fmin(fmin(TX(a), TY(b)), tb);
+                valid = p0 < tb;
+                qx = nx + (r.d[0] > 0.0 ? a : -a);
+                qy = ny + (r.d[1] > 0.0 ? b : -b);
+            }
+            const int last = ls > 0 ? (N >> ls) - 1 : N - 2;
+            qx = min(max(qx, 0), last);
+            qy = min(max(qy, 0), last);
+            bool stop = false, hit = false;
+            Hit hs;
+            if (valid) {
+                float M, t00 = 0.f, t10 = 0.f, t01 = 0.f, t11 = 0.f;
+                if (ls > 0) M = mip[level_offset(L, ls) + qy * (N >> ls) + qx];
+                else M = cell_texels(tex, N, qx, qy, t00, t10, t01, t11);
+                const double za = r.o[2] + p0 * r.d[2], zb = r.o[2] + p1 * r.d[2];
+                if (!(fmin(za, zb) > (double)M)) {
+                    stop = true;  // the ray reaches below the node's maximum
+                    if (ls == 0) hit = patch_hit(r, c, k, qx, qy, p0, p1, za, ta, t00, t10, t01, t11, hs);
+                }
+            }
+            const int lane = __lane_id(), base = lane & ~(G - 1);
+            const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << (G & 63)) - 1)) << base;
+            const uint64_t hits = __ballot(hit) & gmask;
+            if (hits) {
+                const int src = __ffsll((unsigned long long)hits) - 1;
+                h.k = __shfl(hs.k, src);
+                h.i = __shfl(hs.i, src);
+                h.j = __shfl(hs.j, src);
+                h.start = __shfl(hs.start, src);
+                h.t = __shfl(hs.t, src);
+                h.u = __shfl(hs.u, src);
+                h.v = __shfl(hs.v, src);
+                h.fp = __shfl(hs.fp, src);
+                return 1;
+            }
+            const uint64_t stops = __ballot(stop) & gmask;
+            int up = -1;  // after an advance: the level to climb to, before the node-change cap
+            if (probe) {
+                // the highest level whose node the ray passes above: continue past it
+                const uint64_t above = __ballot(valid && !stop) & gmask;
+                if (above) {
+                    const int src = __ffsll((unsigned long long)above) - 1;
+                    t = __shfl(p1, src);
+                    up = l - (src - base) + 1;
+                    probe = false;
+                } else if (l - (G - 1) > 0) {
+                    l -= G;  // below the maxima of all probed levels: probe further down
+                    continue;
+                } else {
+                    t = __shfl(p1, base + l);  // the level-0 cell had no root
+                    up = 0;
+                    probe = false;
+                }
+            } else if (l > 0 && stops) {
+                // descend into the first node the ray dips into, at the point it enters it
+                t = __shfl(p0, __ffsll((unsigned long long)stops) - 1);
+                l -= 1;
+                probe = true;
+            } else {
+                // every node of the batch passed (at level 0: no cell held a root)
+                t = __shfl(p1, base + G - 1);
+                up = (l == 0 && stops) ? 0 : l + 1;  // climb again unless the ray ran below cell tops
+            }
+            if (t >= tb) return 0;
+            t1 = piece_end(r, c, t, tb);
+            int ni, nj;
+            cell_at(r, c, 0.5 * (t + t1), ni, nj);
+            if (up >= 0) {
+                // as in the single-lane walk, never climb into a node that holds the previous
+                // cell: that node's maximum was just found above the ray
+                const unsigned diff = (unsigned)((ni ^ ci) | (nj ^ cj));
+                l = min(min(up, L), diff ? 31 - __clz(diff) : 0);
+            }
+            ci = ni;
+            cj = nj;
+            continue;
+        }
         // Node maximum: from the max-mipmap above level 0; at level 0 from the cell's own four
         // texels (the same value the pyramid holds there), which the patch test needs anyway,
         // so a cell costs one round of loads instead of two.
         float M, t00 = 0.f, t10 = 0.f, t01 = 0.f, t11 = 0.f;
-        if (l > 0) {
-            M = mip[level_offset(L, l) + (cj >> l) * (N >> l) + (ci >> l)];
-        } else {
-            const int64_t b = (int64_t)cj * N + ci;
-            t00 = tex[b];
-            t10 = tex[b + 1];
-            t01 = tex[b + N];
-            t11 = tex[b + N + 1];
-            M = (isfinite(t00) && isfinite(t10) && isfinite(t01) && isfinite(t11))
-                    ? fmaxf(fmaxf(t00, t10), fmaxf(t01, t11)) : -INFINITY;
-        }
+        if (l > 0) M = mip[level_offset(L, l) + (cj >> l) * (N >> l) + (ci >> l)];
+        else M = cell_texels(tex, N, ci, cj, t00, t10, t01, t11);
         const double te = fmax(node_exit(r, c, ci, cj, l, tb), t1);
         const double za = r.o[2] + t * r.d[2], zb = r.o[2] + te * r.d[2];
         bool advance = false, close = false;
@@ -190,31 +356,12 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
         } else if (l > 0) {
             --l;
         } else {
-            const double h00 = t00, h10 = t10, h01 = t01, h11 = t11;
-            const double u0 = ((r.o[0] + t * r.d[0]) - c.x0) * c.inv_hx - ci;
-            const double v0 = ((r.o[1] + t * r.d[1]) - c.y0) * c.inv_hy - cj;
-            const double du = r.d[0] * c.inv_hx, dv = r.d[1] * c.inv_hy;
-            const double A = h10 - h00, B = h01 - h00, C = (h00 - h10) - (h01 - h11);
-            const double cc = za - (h00 + A * u0 + B * v0 + C * u0 * v0);
-            const double bb = r.d[2] - A * du - B * dv - C * (u0 * dv + v0 * du);
-            const double aa = -C * du * dv;
-            double tau = 0.0;
-            if (cc <= 0.0 || smallest_root(aa, bb, cc, te - t, tau)) {
-                h.k = k;
-                h.i = ci;
-                h.j = cj;
-                h.t = t + tau;
-                h.u = u0 + tau * du;
-                h.v = v0 + tau * dv;
-                h.fp = 2.0 * aa * tau + bb;
-                h.start = (cc <= 0.0 && t == ta);
-                return true;
-            }
+            if (patch_hit(r, c, k, ci, cj, t, te, za, ta, t00, t10, t01, t11, h)) return 1;
             advance = true;
             close = true;  // the ray passed below this cell's highest texel
         }
         if (advance) {
-            if (te >= tb) return false;
+            if (te >= tb) return 0;
             t = te;
             t1 = piece_end(r, c, t, tb);
             int ni, nj;
@@ -228,20 +375,22 @@ __device__ bool first_hit(const Ray& r, const RayCas& c, int k, const float* __r
             if (diff) l = min(31 - __clz(diff), l + (close ? 0 : 1));
         }
     }
-    return false;
+    return 0;
 }
 
 // Pixel (col, row) of one view.  In the adjoint every lane of the wave must
 // call it (the gradient scatter uses wave-wide shuffles), also lanes
-// outside the image.
-template <bool BACKWARD>
-__device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row, const float* __restrict__ tex,
+// outside the image.  G lanes (an aligned group, s = 0 .. G - 1) may share a
+// pixel (see first_hit); lane s = 0 writes its results.  Returns true when
+// the step budget ran out: nothing is written for the pixel then.
+template <bool BACKWARD, int G>
+__device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row, const float* __restrict__ tex,
                                               const float* __restrict__ mip, float* __restrict__ depth,
                                               int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                              float* __restrict__ gtex)
+                                              float* __restrict__ gtex, int s, int budget)
 {
     const bool in_image = col < A.W && row < A.H;
-    if (!BACKWARD && !in_image) return;
+    if (!BACKWARD && !in_image) return false;
     const int64_t p = (int64_t)row * A.W + col;
     float g = 0.0f;
     if (BACKWARD && in_image) g = gdepth[p];
@@ -273,7 +422,7 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
     int hid = -1;
     Hit HA, HB;
     HB.k = -1;
-    bool found = false;
+    bool found = false, deferred = false;
     const double dd = r.d[0] * A.c[0].vx + r.d[1] * A.c[0].vy;
     const bool fwd = dd >= 0.0;
     // Cascades in the order the ray's offset sweeps them: increasing k when the offset
@@ -285,15 +434,20 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
         const bool up = pass == 0;
         const bool mine = live && tin < tout && fwd == up;
         if (__ballot(mine) == 0) continue;
-        for (int s = 0; s < A.K; ++s) {
+        for (int step = 0; step < A.K; ++step) {
             if (!mine || found) continue;
-            const int k = up ? s : A.K - 1 - s;
+            const int k = up ? step : A.K - 1 - step;
             const RayCas& ck = A.c[k];
             double ta, tb;
             segment(r, ck, ck.near_d, ck.far_d, tin, tout, ta, tb);
             const int64_t NN = (int64_t)A.N * A.N, MM = (4 * NN - 1) / 3;
-            if (!first_hit(r, ck, k, tex + k * NN, mip + k * MM, ta, tb, HA)) continue;
+            const int sa = first_hit<G>(r, ck, k, tex + k * NN, mip + k * MM, ta, tb, HA, budget, s);
+            if (sa == 0) continue;
             found = true;
+            if (sa < 0) {
+                deferred = true;
+                continue;
+            }
             hid = (HA.k << 26) | (HA.j << 13) | HA.i;
             out_t = HA.t;
             cA = 1.0;
@@ -305,7 +459,11 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
                 if (up ? dA >= lo : dA <= hi) {
                     double tb0, tb1;
                     segment(r, A.c[pk], lo, hi, tin, tout, tb0, tb1);
-                    if (first_hit(r, A.c[pk], pk, tex + pk * NN, mip + pk * MM, tb0, tb1, HB)) {
+                    const int sb = first_hit<G>(r, A.c[pk], pk, tex + pk * NN, mip + pk * MM, tb0, tb1, HB,
+                                                      budget, s);
+                    if (sb < 0) {
+                        deferred = true;
+                    } else if (sb > 0) {
                         const double delta = hi - lo;
                         double al = (dA - lo) / delta, dal = dd / delta;
                         if (al <= 0.0) { al = 0.0; dal = 0.0; }
@@ -327,9 +485,11 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
         }
     }
     if (!BACKWARD) {
-        depth[p] = (float)out_t;
-        hit[p] = hid;
-        return;
+        if (!deferred && s == 0) {
+            depth[p] = (float)out_t;
+            hit[p] = hid;
+        }
+        return deferred;
     }
     // gradient scatter: wave-combined for lanes that share a cell (common near
     // the camera, where many pixels land in one texture cell), direct atomics
@@ -338,7 +498,7 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
     for (int x = 0; x < 2; ++x) {
         const Hit& H = x ? HB : HA;
         const double cf = x ? cB : cA;
-        const bool has = found && H.k >= 0 && !H.start && H.fp < 0.0 && cf != 0.0;
+        const bool has = found && !deferred && s == 0 && H.k >= 0 && !H.start && H.fp < 0.0 && cf != 0.0;
         float w[4] = {0.f, 0.f, 0.f, 0.f};
         int key = -1;
         if (has) {
@@ -384,16 +544,62 @@ __device__ __forceinline__ void raycast_pixel(const RayArgs& A, int col, int row
             atomicAdd(&gk[b + N + 1], w[3]);
         }
     }
+    return deferred;
 }
 
+// Frame kernel: one lane per pixel (6 waves per SIMD for the forward pass:
+// at most 80 VGPRs).  With a workspace (work[0] = queue length, work[1]
+// unused, work[2 ..] = pixel indices) a pixel whose walk exceeds RAY_BUDGET
+// steps is queued instead of finished.
 template <bool BACKWARD>
-__global__ __launch_bounds__(256) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
+__global__ __launch_bounds__(256, BACKWARD ? 4 : 6) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
                                                       const float* __restrict__ mip, float* __restrict__ depth,
                                                       int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                                      float* __restrict__ gtex)
+                                                      float* __restrict__ gtex, int* __restrict__ work)
 {
-    raycast_pixel<BACKWARD>(A, blockIdx.x * 16 + threadIdx.x, blockIdx.y * 16 + threadIdx.y, tex, mip, depth, hit,
-                            gdepth, gtex);
+    const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
+    const bool deferred = raycast_pixel<BACKWARD, 1>(A, col, row, tex, mip, depth, hit, gdepth, gtex, 0,
+                                                     work ? RAY_BUDGET : INT_MAX);
+    if (!work) return;
+    const uint64_t m = __ballot(deferred);  // one queue reservation per wave
+    if (!m) return;
+    const int lane = __lane_id(), leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&work[0], __popcll(m));
+    base = __shfl(base, leader);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (deferred) work[2 + base + __popcll(m & lt)] = row * A.W + col;
+}
+
+// Queued pixels, RAY_SPLIT lanes each.  The queue is complete when this
+// kernel starts, so wave w takes entries (w + j W) 64 / RAY_SPLIT onwards for
+// j = 0, 1, ... (W waves in the grid): no atomics on a shared counter.  The
+// loop condition is wave-uniform; a lane group whose entry lies past the
+// queue's end walks nothing but stays with its wave (the adjoint's scatter
+// uses wave-wide shuffles).
+template <bool BACKWARD>
+__global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const float* __restrict__ tex,
+                                                           const float* __restrict__ mip, float* __restrict__ depth,
+                                                           int32_t* __restrict__ hit, const float* __restrict__ gdepth,
+                                                           float* __restrict__ gtex, int* __restrict__ work)
+{
+    constexpr int G = RAY_SPLIT, PER_WAVE = 64 / G;
+    const int lane = __lane_id(), s = lane & (G - 1);
+    const int count = __builtin_amdgcn_readfirstlane(work[0]);
+    const int waves = (int)(gridDim.x * (blockDim.x / 64));
+    const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+    for (int first = wave * PER_WAVE; first < count; first += waves * PER_WAVE) {
+        const int idx = first + lane / G;
+        const bool has = idx < count;
+        const int p = has ? work[2 + idx] : 0;
+        raycast_pixel<BACKWARD, G>(A, has ? p % A.W : A.W, has ? p / A.W : 0, tex, mip, depth, hit, gdepth, gtex, s,
+                                   INT_MAX);
+    }
+}
+
+__global__ void zero_queue_kernel(int* __restrict__ work)
+{
+    if (threadIdx.x == 0) work[0] = 0;
 }
 
 // Persistent form over every view of a batch: each wave takes runs of
@@ -428,8 +634,8 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
             const BatchView& V = as_constant(P.views, v);
             const int local = w - v_lo;
             const int tx = local % V.tiles_x, ty = local / V.tiles_x;
-            raycast_pixel<BACKWARD>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,
-                                    V.gdepth, V.gtex);
+            raycast_pixel<BACKWARD, 1>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,
+                                       V.gdepth, V.gtex, 0, INT_MAX);
         }
     }
 }
@@ -478,30 +684,47 @@ hfr_status ray_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_casc
 }
 
 
+namespace {
+
+// The frame kernel, then (with a workspace) the queue of long rays.
+template <bool BACKWARD>
+void launch_raycast(const RayArgs& A, const float* tex, const float* mip, float* depth, int32_t* hit,
+                    const float* gdepth, float* gtex, int32_t* work, hipStream_t s)
+{
+    if (work) zero_queue_kernel<<<1, 64, 0, s>>>(work);
+    const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
+    raycast_kernel<BACKWARD><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work);
+    if (!work) return;
+    // persistent: enough lane groups that a typical queue is taken in one round
+    const int64_t pixels = (int64_t)A.W * A.H;
+    const int blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(64, pixels / 1024));
+    raycast_tail_kernel<BACKWARD><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work);
+}
+
+}  // namespace
+
 extern "C" hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
-                                  const float* tex, const float* mip, float* depth, int32_t* hit, hfr_stream stream)
+                                  const float* tex, const float* mip, float* depth, int32_t* hit, int32_t* work,
+                                  hfr_stream stream)
 {
     RayArgs A;
     hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
-    const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
-    raycast_kernel<false><<<grid, dim3(16, 16), 0, (hipStream_t)stream>>>(A, tex, mip, depth, hit, nullptr, nullptr);
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast");
     return hfr_ok();
 }
 
 extern "C" hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
                                            int32_t K, const float* tex, const float* mip, const float* grad_depth,
-                                           float* grad_tex, hfr_stream stream)
+                                           float* grad_tex, int32_t* work, hfr_stream stream)
 {
     RayArgs A;
     hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && grad_depth && grad_tex, "NULL texture, mipmap or gradient");
-    const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
-    raycast_kernel<true><<<grid, dim3(16, 16), 0, (hipStream_t)stream>>>(A, tex, mip, nullptr, nullptr, grad_depth,
-                                                                         grad_tex);
+    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work, (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_backward");
     return hfr_ok();
 }

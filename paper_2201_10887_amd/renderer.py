@@ -2,9 +2,10 @@
 
 ``Renderer`` owns the device-resident heightfield (leaves, level
 index, per-level truncation radii) and the per-frame buffers (cascade textures,
-visibility bits, max-mipmaps), all allocated once; ``forward`` runs cascade
-fitting (host), discretize, max-mipmap and ray casting (device) on the
-current stream and allocates nothing.  ``RenderDepth`` is the
+visibility bits, max-mipmaps, and per image size the ray caster's long-ray
+queue), all allocated once; ``forward`` runs cascade fitting (host),
+discretize, max-mipmap and ray casting (device) on the current stream and
+allocates nothing after the first frame of an image size.  ``RenderDepth`` is the
 ``torch.autograd.Function`` that takes an image loss back to leaf values and
 Gaussian widths through the hand-written adjoints.
 """
@@ -32,6 +33,60 @@ class Renderer:
         self.mask = torch.empty((K, N, (N + 31) // 32), dtype=torch.int32, device=device)
         self.mip = torch.empty((K, api.mip_size(N)), dtype=torch.float32, device=device)
         self.device = device
+        # queue long rays for lane-shared walking (forward, adjoint); False: every ray finishes
+        # on its own lane.  tune_raycast picks each by timing both on a camera.
+        self.long_ray_queue = True
+        self.long_ray_queue_backward = True
+        self._work = {}
+
+    def ray_work(self, cam, backward: bool = False):
+        """The long-ray queue for this camera's image size (None when disabled)."""
+        if not (self.long_ray_queue_backward if backward else self.long_ray_queue):
+            return None
+        key = (cam.width, cam.height)
+        if key not in self._work:
+            self._work[key] = api.ray_workspace(cam, self.device)
+        return self._work[key]
+
+    def tune_raycast(self, cam, reps: int = 5) -> dict:
+        """Time the ray cast and its adjoint with and without the long-ray queue on this camera's
+        frame and keep the faster of each.  The queue pays off when a few long rays set the frame
+        time; when the frame is throughput-bound, walking them after the rest costs more than it
+        saves.  Returns the median times (ms)."""
+        import torch
+        cas = self.fit(cam)
+        api.discretize(self.L, self.dom, cas, self.tex, self.mask)
+        api.build_maxmip(self.tex, self.mip)
+        depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=self.device)
+        hit = torch.empty((cam.height, cam.width), dtype=torch.int32, device=self.device)
+        work = api.ray_workspace(cam, self.device)
+        api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, None, None)
+        gd = torch.isfinite(depth).float()
+        gtex = torch.zeros_like(self.tex)
+
+        def median_ms(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            return sorted(ts)[len(ts) // 2]
+
+        res = {}
+        for name, wk in (("single_lane", None), ("queue", work)):
+            res[f"raycast_{name}"] = median_ms(
+                lambda: api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, None, wk))
+            res[f"raycast_backward_{name}"] = median_ms(
+                lambda: api.raycast_backward(cam, self.dom, cas, self.tex, self.mip, gd, gtex, None, wk))
+        self.long_ray_queue = res["raycast_queue"] < res["raycast_single_lane"]
+        self.long_ray_queue_backward = res["raycast_backward_queue"] < res["raycast_backward_single_lane"]
+        self._work[(cam.width, cam.height)] = work
+        return {k: round(v, 4) for k, v in res.items()}
 
     @property
     def domain(self):
@@ -48,12 +103,13 @@ class Renderer:
         cas = self.fit(cam) if cascades is None else cascades
         api.discretize(self.L, self.dom, cas, self.tex, self.mask, stream)
         api.build_maxmip(self.tex, self.mip, stream)
-        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream)
+        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream, self.ray_work(cam))
         return depth, hit, cas
 
     def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None):
         """Accumulates into the (caller-zeroed) gradient buffers."""
-        api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream)
+        api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream,
+                             self.ray_work(cam, backward=True))
         api.discretize_backward(self.L, self.dom, cascades, self.tex, grad_tex, grad_v, grad_sigma, stream)
         return grad_v, grad_sigma
 

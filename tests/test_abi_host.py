@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 4
+    assert api.abi_version() == 5
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -189,15 +189,19 @@ def test_invalid_arguments_rejected_before_launch():
     # cascades with different N
     bad = (api.Cascade * 2)(cs[0], cs[1])
     bad[1].n = 128
-    _raise_einval("hfr_raycast", ctypes.byref(cam), ctypes.byref(dom), bad, 2, dummy, dummy, dummy, dummy, None)
+    _raise_einval("hfr_raycast", ctypes.byref(cam), ctypes.byref(dom), bad, 2, dummy, dummy, dummy, dummy, None,
+                  None)
     # image too large, NaN camera
     big = api.camera(synth.Camera((0, 0, 10), 0.0, -0.3, 1.0, 20000, 64))
-    _raise_einval("hfr_raycast", ctypes.byref(big), ctypes.byref(dom), cs, 2, dummy, dummy, dummy, dummy, None)
+    _raise_einval("hfr_raycast", ctypes.byref(big), ctypes.byref(dom), cs, 2, dummy, dummy, dummy, dummy, None,
+                  None)
     nan = api.camera(synth.Camera((float("nan"), 0, 10), 0.0, -0.3, 1.0, 64, 64))
-    _raise_einval("hfr_raycast", ctypes.byref(nan), ctypes.byref(dom), cs, 2, dummy, dummy, dummy, dummy, None)
+    _raise_einval("hfr_raycast", ctypes.byref(nan), ctypes.byref(dom), cs, 2, dummy, dummy, dummy, dummy, None,
+                  None)
     # empty domain
     empty = api.domain(synth.Domain(0, 0, 0, 100, 0, 10))
-    _raise_einval("hfr_raycast", ctypes.byref(cam), ctypes.byref(empty), cs, 2, dummy, dummy, dummy, dummy, None)
+    _raise_einval("hfr_raycast", ctypes.byref(cam), ctypes.byref(empty), cs, 2, dummy, dummy, dummy, dummy, None,
+                  None)
     # discretize: missing level index, bad cutoff, bad depth
     L = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, dummy, 4, 3.5, 0.0, 0.0, 1.0)
     _raise_einval("hfr_discretize", ctypes.byref(L), ctypes.byref(dom), cs, 2, dummy, None, None)
@@ -222,7 +226,7 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 4
+    assert lib.hfr_abi_version() == 5
 
 
 def test_batch_arguments_rejected_before_any_device_call():

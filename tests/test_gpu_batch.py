@@ -71,7 +71,7 @@ def batch(gpu, tiny_scene):
 
 
 def single_view(R, v, cam, grad_depth=None):
-    """The per-view entry points on the batch's cascades."""
+    """The per-view entry points on the batch's cascades (the single-lane ray walk, as in the batch)."""
     import torch
     spec = R.specs[v]
     f = R.fields[spec.field]
@@ -80,10 +80,10 @@ def single_view(R, v, cam, grad_depth=None):
     mask = torch.zeros((K, N, (N + 31) // 32), dtype=torch.int32, device="cuda")
     tex = api.discretize(f.L, f.dom, cas, mask=mask)
     mip = api.build_maxmip(tex)
-    depth, hit = api.raycast(cam, f.dom, cas, tex, mip)
+    depth, hit = api.raycast(cam, f.dom, cas, tex, mip, work=None)
     out = {"tex": tex, "mask": mask, "mip": mip, "depth": depth, "hit": hit, "cas": cas}
     if grad_depth is not None:
-        gtex = api.raycast_backward(cam, f.dom, cas, tex, mip, grad_depth)
+        gtex = api.raycast_backward(cam, f.dom, cas, tex, mip, grad_depth, work=None)
         out["gv"], out["gs"] = api.discretize_backward(f.L, f.dom, cas, tex, gtex)
     return out
 

@@ -113,6 +113,30 @@ def test_raycast_full_frame_sampled(gpu, medium, standin):
     assert np.isfinite(ref["depth"]).mean() > 0.3
 
 
+def test_long_ray_queue_matches_single_lane_walk(gpu, medium, standin):
+    """The queued walk of long rays, lanes sharing each ray, gives the single-lane walk's results."""
+    m = medium
+    cam = m["cam"]
+    tex = gpu.as_tensor(standin, device="cuda")
+    mip = api.build_maxmip(tex)
+    d0, h0 = api.raycast(cam, m["dom"], m["cas"], tex, mip, work=None)
+    work = api.ray_workspace(cam, "cuda")
+    d1, h1 = api.raycast(cam, m["dom"], m["cas"], tex, mip, work=work)
+    queued = int(work[0].item())
+    assert 1000 < queued < cam.width * cam.height // 20, queued  # long rays exist and were queued
+    d0, d1, h0, h1 = (a.cpu().numpy() for a in (d0, d1, h0, h1))
+    fin = np.isfinite(d0)
+    assert np.array_equal(fin, np.isfinite(d1))
+    assert (h0 != h1).mean() <= 1e-5
+    assert np.max(np.abs(d0[fin] - d1[fin]) / np.abs(d0[fin])) <= 1e-6
+    rng = np.random.default_rng(13)
+    gd = gpu.as_tensor((rng.normal(0, 1, d0.shape) * fin).astype(np.float32), device="cuda")
+    g0 = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip, gd, work=None).cpu().numpy()
+    g1 = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip, gd, work=work).cpu().numpy()
+    err, per = G.grad_close(g1, g0)
+    assert err <= 1e-5 and per.mean() >= 0.9999, (err, per.mean())
+
+
 def test_backward_full_frame_sampled(gpu, medium, standin):
     m = medium
     cam = m["cam"]
