@@ -438,15 +438,36 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     tex[(int64_t)j * N + i] = out;
 }
 
-// 8 waves per SIMD (64 VGPRs, no spills; 8 blocks of LDS fit a CU): the near
-// cascades wait on node-table and record loads, and more resident waves hide that.
-__global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+// Up to FUSE cascades of one view in one launch.  Their block rows are
+// interleaved (row v holds row v / K of cascade v % K) before the XCD-aware
+// mapping, so every XCD's contiguous share mixes the cascades (the far ones
+// cost the most) while neighbouring rows of a cascade stay on one XCD; the
+// latency-bound blocks of the near cascades overlap the ALU-bound far ones.
+constexpr int FUSE = 4;
+struct CascadeSet {
+    TexCascade c[FUSE];
+    int K;
+};
+
+__device__ inline int fused_block(const CascadeSet& S, int gx, int gy, int* bx, int* by)
+{
+    int row;
+    xcd_tile(blockIdx.x, gx, gy * S.K, bx, &row);
+    *by = row / S.K;
+    return row - *by * S.K;
+}
+
+// 8 waves per SIMD (at most 64 VGPRs, no spills; 8 blocks of LDS fit a CU): the near
+// cascades wait on rank-table and record loads, and more resident waves hide that.
+__global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, CascadeSet S, Dom2 D, int gx, int gy,
                                                          float* __restrict__ tex, uint16_t* __restrict__ mask)
 {
     __shared__ DiscShared sh;
     int bx, by;
-    xcd_tile(blockIdx.x, gx, gy, &bx, &by);
-    discretize_block(T, C, D, bx, by, tex, mask, sh);
+    const int k = __builtin_amdgcn_readfirstlane(fused_block(S, gx, gy, &bx, &by));
+    const TexCascade& C = S.c[k];
+    const int64_t N = C.n;
+    discretize_block(T, C, D, bx, by, tex + k * N * N, mask ? mask + k * N * 2 * ((N + 31) / 32) : nullptr, sh);
 }
 
 // Adjoint of Eq. 2 / Eq. 1.  Lanes first own texels (S0 of each texel), then
@@ -573,15 +594,17 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     }
 }
 
-__global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, TexCascade C, Dom2 D, int gx, int gy,
+__global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, CascadeSet S, Dom2 D, int gx, int gy,
                                                                   const float* __restrict__ tex,
                                                                   const float* __restrict__ gtex,
                                                                   float* __restrict__ gv, float* __restrict__ gs)
 {
     __shared__ DiscBwdShared sh;
     int bx, by;
-    xcd_tile(blockIdx.x, gx, gy, &bx, &by);
-    discretize_backward_block(T, C, D, bx, by, tex, gtex, gv, gs, sh);
+    const int k = __builtin_amdgcn_readfirstlane(fused_block(S, gx, gy, &bx, &by));
+    const TexCascade& C = S.c[k];
+    const int64_t N = C.n;
+    discretize_backward_block(T, C, D, bx, by, tex + k * N * N, gtex + k * N * N, gv, gs, sh);
 }
 
 // Persistent form over every cascade of every view of a batch: each
@@ -684,10 +707,13 @@ extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom,
     const Dom2 D{dom->x0, dom->y0, dom->x1, dom->y1};
     const int gx = (N + BS - 1) / BS, gy = (N + BS - 1) / BS;
     const int words = (N + 31) / 32;
-    for (int k = 0; k < K; ++k) {
-        discretize_kernel<<<dim3(gx * gy), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
-            T, tex_cascade(cas[k]), D, gx, gy, tex + (int64_t)k * N * N,
-            mask ? reinterpret_cast<uint16_t*>(mask + (int64_t)k * N * words) : nullptr);
+    for (int k0 = 0; k0 < K; k0 += FUSE) {
+        CascadeSet S;
+        S.K = std::min(FUSE, K - k0);
+        for (int k = 0; k < S.K; ++k) S.c[k] = tex_cascade(cas[k0 + k]);
+        discretize_kernel<<<dim3(gx * gy * S.K), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
+            T, S, D, gx, gy, tex + (int64_t)k0 * N * N,
+            mask ? reinterpret_cast<uint16_t*>(mask + (int64_t)k0 * N * words) : nullptr);
         HFR_LAUNCH_CHECK("discretize");
     }
     return hfr_ok();
@@ -706,10 +732,12 @@ extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_dom
     const int N = cas[0].n;
     const Dom2 D{dom->x0, dom->y0, dom->x1, dom->y1};
     const int gx = (N + BS - 1) / BS, gy = (N + BS - 1) / BS;
-    for (int k = 0; k < K; ++k) {
-        discretize_backward_kernel<<<dim3(gx * gy), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
-            T, tex_cascade(cas[k]), D, gx, gy, tex + (int64_t)k * N * N, grad_tex + (int64_t)k * N * N, grad_v,
-            grad_sigma);
+    for (int k0 = 0; k0 < K; k0 += FUSE) {
+        CascadeSet S;
+        S.K = std::min(FUSE, K - k0);
+        for (int k = 0; k < S.K; ++k) S.c[k] = tex_cascade(cas[k0 + k]);
+        discretize_backward_kernel<<<dim3(gx * gy * S.K), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
+            T, S, D, gx, gy, tex + (int64_t)k0 * N * N, grad_tex + (int64_t)k0 * N * N, grad_v, grad_sigma);
         HFR_LAUNCH_CHECK("discretize_backward");
     }
     return hfr_ok();
