@@ -210,9 +210,10 @@ hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_
 
 /* ------------------------------------------------------- per frame (device) */
 
-/* Writes L->packed (gathered through L->order) and L->level_radius from x,
- * y, v, c, sigma and cutoff (call again whenever v or sigma change).  EINVAL
- * on NULL pointers, n < 1, cutoff <= 0, max_depth outside [0, 15]. */
+/* Writes L->packed (each record placed at its leaf's sorted position, found
+ * through L->rank) and L->level_radius from x, y, v, c, sigma and cutoff
+ * (call again whenever v or sigma change).  EINVAL on NULL pointers, n < 1,
+ * cutoff <= 0, max_depth outside [0, 15]. */
 hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
 
 /* Discretization (Section 4, Eq. 1 and Eq. 2, and the visibility texture of

@@ -52,6 +52,24 @@ def test_library_quadtree_and_fit_match(medium):
             assert abs(getattr(a, f_lib) - getattr(b, f_ora)) <= 1e-9 * medium["dom"].extent
 
 
+def test_packed_records_follow_the_level_order(gpu, medium):
+    """hfr_pack_leaves: record p holds leaf order[p] (x, y, v exactly, s within one FP32 rounding),
+    the level radii are the largest cutoff sigma c per level."""
+    m, L, w = medium, medium["L"], medium["w"]
+    order = L.order.cpu().numpy()
+    packed = L.packed.cpu().numpy()
+    lv = m["leaves"]
+    for col, key in ((0, "x"), (1, "y"), (2, "v")):
+        assert np.array_equal(packed[:, col], lv[key][order]), key
+    s = np.sqrt(np.float64(np.log2(np.e) / 2)) / (lv["sigma"][order].astype(np.float64) * lv["c"][order])
+    assert np.all(np.abs(packed[:, 3] - s) <= 2 * np.spacing(s.astype(np.float32))), "scale"
+    radius = L.level_radius.cpu().numpy()
+    for level in range(w.max_depth + 1):
+        at = lv["level"] == level
+        want = w.cutoff * float((lv["sigma"][at] * lv["c"][at]).max()) if at.any() else 0.0
+        assert abs(radius[level] - want * 1.00001) <= 1e-5 * max(want, 1.0), level
+
+
 def test_discretize_full_frame_sampled(gpu, medium):
     m = medium
     K, N = len(m["cas"]), m["cas"][0].n
