@@ -191,11 +191,12 @@ def cpu_baseline(w, leaves, cam, R, cas, vis_texels, seconds=12.0):
         oray.cast_rays(np.asarray(cam.pos), dirs, dom, ocs, tex, threads=1)
         t_ray += time.perf_counter() - t0
         n_ray += len(dirs)
-    ms = 1e3 * (t_disc / n_tex * vis_texels + t_ray / n_ray * cam.width * cam.height)
+    surfaces = 1 + len(R.extra)  # every surface costs the oracle one approximation and one ray cast
+    ms = surfaces * 1e3 * (t_disc / n_tex * vis_texels + t_ray / n_ray * cam.width * cam.height)
     return {"value": round(ms, 1), "unit": "ms/frame", "cores": 1, "kind": "oracle",
             "sample": f"{n_tex} texels (Eq. 2, FP64 NumPy) + {n_ray} rays (FP64 C walk over raster-resampled "
                       f"stand-in textures), one thread, scaled to {vis_texels} visible texels and "
-                      f"{cam.width}x{cam.height} rays"}
+                      f"{cam.width}x{cam.height} rays" + (f", times {surfaces} surfaces" if surfaces > 1 else "")}
 
 
 def fit_tau(dem, side, depth, target, rel=0.15, iters=24):
@@ -353,6 +354,8 @@ def main():
     build_scene.dem_cache = dem
     t0 = time.time()
     R = Renderer(leaves, w.side, w.max_depth, w.cutoff, w.cascades, w.tex_n, w.split_lambda, w.overlap)
+    if w.water_seed:  # a second surface on the same cells, drawn where nearer
+        R.add_surface(synth.water_surface(leaves, w.side, w.water_seed, w.water_wet))
     torch.cuda.synchronize()
     print(f"[bench] renderer ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
@@ -380,7 +383,7 @@ def main():
         gtex.zero_()
         gv.zero_()
         gs.zero_()
-        R.backward(cam, c, grad_depth, gtex, gv, gs)
+        R.backward(cam, c, grad_depth, gtex, gv, gs, hit=hit)
 
     for _ in range(args.warmup):
         forward()
@@ -398,6 +401,20 @@ def main():
                                                          R.ray_work(cam, backward=True)),
         "discretize_backward": lambda: api.discretize_backward(R.L, R.dom, cas, R.tex, gtex, gv, gs),
     }
+    if R.extra:
+        X = R.extra[0]
+        d_ter, h_ter = api.raycast(cam, R.dom, cas, R.tex, R.mip, None, None, None, R.ray_work(cam))
+
+        def nearer():  # from the terrain-only image each time (two 8 MB copies included)
+            depth.copy_(d_ter)
+            hit.copy_(h_ter)
+            api.raycast_nearer(cam, R.dom, cas, X["tex"], X["mip"], 1, depth, hit, None, R.ray_work(cam))
+
+        stage.update({
+            "discretize_water": lambda: api.discretize(X["L"], R.dom, cas, X["tex"], X["mask"]),
+            "build_maxmip_water": lambda: api.build_maxmip(X["tex"], X["mip"]),
+            "raycast_nearer_water": nearer,
+        })
     stage_ms = {k: timed(f, args.steps, stream) for k, f in stage.items()}
     api.discretize(R.L, R.dom, cas, R.tex, R.mask)
     torch.cuda.synchronize()
@@ -408,7 +425,10 @@ def main():
 
     work = discretize_work(R, cas, leaves, w)
     vis_texels, pairs = work["visible_texels"], work["pairs"]
+    forward()  # leave the full frame (every surface) in depth / hit
+    torch.cuda.synchronize()
     hits = int(torch.isfinite(depth).sum())
+    water_px = int(((hit >= 0) & ((hit >> 29) == 1)).sum()) if R.extra else 0
     K = R.K
     t_disc = stage_ms["discretize"] * 1e-3
     t_alu_floor = work["flops"] / (FP32_PEAK_TFLOPS * 1e12)
@@ -455,6 +475,8 @@ def main():
         "gtexel_per_s_all": round(K * R.N * R.N / (stage_ms["discretize"] * 1e-3) / 1e9, 3),
         "grays_per_s": round(W * H / (stage_ms["raycast"] * 1e-3) / 1e9, 3),
         "hit_fraction": round(hits / (W * H), 4),
+        "surfaces": 1 + len(R.extra),
+        "water_pixel_fraction": round(water_px / (W * H), 4) if R.extra else None,
         "visible_texels": vis_texels,
         "pairs": round(pairs),
         "mean_influencers": round(work["mean_influencers"], 2),

@@ -38,10 +38,11 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 5
+#define HFR_ABI_VERSION 6
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
+#define HFR_MAX_SURFACES 4
 
 typedef int32_t hfr_status;
 enum {
@@ -249,8 +250,9 @@ hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, float* mip, 
  * there gives depth (1 - a) t_nearer + a t_farther with
  * a = clamp((d(t_A) - split) / (far - split), 0, 1) of the nearer cascade.
  * depth: device float[H][W], +inf on a miss.  hit: device int32[H][W],
- * (k << 26) | (j << 13) | i of hit A's cell, -1 on a miss.  Geometry is
- * FP64 throughout.
+ * (s << 29) | (k << 26) | (j << 13) | i of hit A's cell (s: the surface
+ * index, 0 here; see hfr_raycast_nearer), -1 on a miss.  Geometry is FP64
+ * throughout.
  * work: device int32[W H + 2] scratch (its contents on entry do not matter;
  * the call overwrites them), or NULL.  With it, a ray still walking after a
  * fixed number of cell steps is queued there and finished by a second
@@ -276,6 +278,34 @@ hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom,
                                 const hfr_cascade* cas, int32_t K, const float* tex,
                                 const float* mip, const float* grad_depth, float* grad_tex,
                                 int32_t* work, hfr_stream stream);
+
+/* Several heightfields per frame (Section 2: the input is a terrain model and
+ * relative water depths on the same adaptive grid; Table 1 times one
+ * approximation pass per heightfield and the ray casting of all of them).
+ * The visible point of a pixel is the nearest first hit over the surfaces.
+ * Draw surface 0 with hfr_raycast, then every further surface s (1 ..
+ * HFR_MAX_SURFACES - 1, its own textures and pyramids over the same
+ * cascades) with hfr_raycast_nearer: each ray is clipped at the depth already
+ * in depth[p], and a hit of surface s that lies in front replaces depth[p]
+ * and hit[p] (tagged with s in bits 29-30); ties keep the earlier surface.
+ * depth, hit: device in/out as written by the previous surfaces.  work: as
+ * for hfr_raycast.  EINVAL: surface outside [1, HFR_MAX_SURFACES - 1], as
+ * for hfr_raycast otherwise. */
+hfr_status hfr_raycast_nearer(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                              int32_t K, const float* tex, const float* mip, int32_t surface,
+                              float* depth, int32_t* hit, int32_t* work, hfr_stream stream);
+
+/* Adjoint of the composite depth with respect to surface s's texels: as
+ * hfr_raycast_backward on surface s's textures, restricted to the pixels
+ * whose final hit (hit, device int32[H][W] as left by the drawing calls)
+ * carries tag s.  A pixel's depth is surface s's first hit there, whatever
+ * other surfaces lie behind, so the walk is recomputed without a clip.
+ * EINVAL: surface outside [0, HFR_MAX_SURFACES - 1], NULL hit. */
+hfr_status hfr_raycast_backward_surface(const hfr_camera* cam, const hfr_domain* dom,
+                                        const hfr_cascade* cas, int32_t K, const float* tex,
+                                        const float* mip, int32_t surface, const int32_t* hit,
+                                        const float* grad_depth, float* grad_tex, int32_t* work,
+                                        hfr_stream stream);
 
 /* Adjoint of hfr_discretize (Eq. 2 and Eq. 1): ACCUMULATES into the
  * caller-zeroed grad_v and grad_sigma (device float[n])

@@ -26,6 +26,8 @@ Modules and the passage each follows:
 * ``adjoint``    -- hand-derived gradients of hit depth with respect to
                     texel heights, and of Eq. 2 with respect to leaf values
                     and widths; central finite differences.
+* ``composite``  -- several heightfields per frame (Section 2's terrain and
+                    water depths, Table 1's passes): the nearest first hit.
 
 Parity status of each function is stated in its docstring ("pinned by ..."
 naming the tests that pin it, or "parity unpinned").

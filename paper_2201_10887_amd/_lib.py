@@ -97,6 +97,8 @@ SIGNATURES = {
     "hfr_build_maxmip": ([P, I32, I32, P, P], I32),
     "hfr_raycast": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
     "hfr_raycast_backward": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
+    "hfr_raycast_nearer": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, I32, P, P, P, P], I32),
+    "hfr_raycast_backward_surface": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, I32, P, P, P, P, P], I32),
     "hfr_discretize_backward": ([PP(Leaves), PP(Domain), PP(Cascade), I32, P, P, P, P, P], I32),
     "hfr_batch_plan_create": ([PP(BatchField), I32, PP(BatchView), I32, PP(P)], I32),
     "hfr_batch_plan_destroy": ([P], None),

@@ -195,6 +195,19 @@ class DeviceLeaves:
         self.max_depth, self.cutoff = int(max_depth), float(cutoff)
         self.x0, self.y0, self.side = float(x0), float(y0), float(side)
 
+    def with_values(self, v) -> "DeviceLeaves":
+        """Another heightfield on the same cells (shares positions, sizes, widths and the level index):
+        values ``v``, its own packed records and level radii (call ``pack_leaves`` on it)."""
+        import torch
+        other = object.__new__(DeviceLeaves)
+        other.__dict__.update(self.__dict__)
+        other.v = torch.as_tensor(np.ascontiguousarray(v, np.float32), device=self.x.device)
+        if other.v.numel() != self.n:
+            raise ValueError("one value per leaf is required")
+        other.packed = torch.empty_like(self.packed)
+        other.level_radius = torch.zeros_like(self.level_radius)
+        return other
+
     def struct(self) -> Leaves:
         import torch
         for name in ("x", "y", "c", "v", "sigma", "packed", "level_radius"):
@@ -275,6 +288,32 @@ def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, gra
         grad_tex = torch.zeros((K, N, N), dtype=torch.float32, device=tex.device)
     call("hfr_raycast_backward", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
          _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
+         _dev(grad_depth, torch.float32, (cam.height, cam.width), "grad_depth"),
+         _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _work_ptr(work, cam, tex.device), _stream(stream))
+    return grad_tex
+
+
+def raycast_nearer(cam, dom, cascades: ctypes.Array, tex, mip, surface: int, depth, hit, stream=None, work=True):
+    """Draw a further surface over ``depth`` / ``hit`` (in place) where it is nearer."""
+    import torch
+    K, N = len(cascades), cascades[0].n
+    call("hfr_raycast_nearer", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"), int(surface),
+         _dev(depth, torch.float32, (cam.height, cam.width), "depth"),
+         _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _work_ptr(work, cam, tex.device), _stream(stream))
+    return depth, hit
+
+
+def raycast_backward_surface(cam, dom, cascades: ctypes.Array, tex, mip, surface: int, hit, grad_depth,
+                             grad_tex=None, stream=None, work=True):
+    """Texel gradients of surface ``surface`` over the pixels whose final hit it is."""
+    import torch
+    K, N = len(cascades), cascades[0].n
+    if grad_tex is None:
+        grad_tex = torch.zeros((K, N, N), dtype=torch.float32, device=tex.device)
+    call("hfr_raycast_backward_surface", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"), int(surface),
+         _dev(hit, torch.int32, (cam.height, cam.width), "hit"),
          _dev(grad_depth, torch.float32, (cam.height, cam.width), "grad_depth"),
          _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _work_ptr(work, cam, tex.device), _stream(stream))
     return grad_tex

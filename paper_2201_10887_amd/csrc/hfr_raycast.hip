@@ -29,6 +29,13 @@ namespace {
 constexpr int RAY_BUDGET = 64;  // cell-walk steps a pixel may take in the frame kernel
 constexpr int RAY_SPLIT = 16;   // lanes that share one queued ray
 
+// Which surface a ray cast draws when a frame holds several heightfields.
+struct SurfaceArgs {
+    int tag;                       // surface index, written into bits 29-30 of every hit
+    bool nearer;                   // forward: clip each ray at depth[p], write only a nearer hit
+    const int32_t* __restrict__ filter;  // adjoint: only pixels whose hit carries this tag (NULL: all)
+};
+
 struct Ray {
     double o[3], d[3], inv_d[2];
 };
@@ -387,13 +394,19 @@ template <bool BACKWARD, int G>
 __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row, const float* __restrict__ tex,
                                               const float* __restrict__ mip, float* __restrict__ depth,
                                               int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                              float* __restrict__ gtex, int s, int budget)
+                                              float* __restrict__ gtex, int s, int budget, const SurfaceArgs& S)
 {
     const bool in_image = col < A.W && row < A.H;
     if (!BACKWARD && !in_image) return false;
     const int64_t p = (int64_t)row * A.W + col;
     float g = 0.0f;
     if (BACKWARD && in_image) g = gdepth[p];
+    if (BACKWARD && in_image && S.filter) {
+        const int32_t hf = S.filter[p];
+        if (hf < 0 || ((hf >> 29) & 3) != S.tag) g = 0.0f;  // another surface is nearer, or none is hit
+    }
+    // the nearer pass sees only what lies in front of the surfaces drawn so far
+    const float clip = (!BACKWARD && S.nearer) ? depth[p] : INFINITY;
     // in the adjoint every lane stays to the end (the scatter uses wave-wide shuffles)
     const bool live = in_image && (!BACKWARD || (g != 0.0f && isfinite(g)));
     const double sx = ((col + 0.5) / A.W) * 2.0 - 1.0;
@@ -417,6 +430,7 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
     if (r.d[2] > 0.0) tout = fmin(tout, (A.zmax - r.o[2]) / r.d[2]);
     else if (r.d[2] < 0.0) tin = fmax(tin, (A.zmax - r.o[2]) / r.d[2]);
     else if (r.o[2] > A.zmax) tin = INFINITY;
+    tout = fmin(tout, (double)clip);
 
     double out_t = INFINITY, cA = 0.0, cB = 0.0;
     int hid = -1;
@@ -448,7 +462,7 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
                 deferred = true;
                 continue;
             }
-            hid = (HA.k << 26) | (HA.j << 13) | HA.i;
+            hid = (S.tag << 29) | (HA.k << 26) | (HA.j << 13) | HA.i;
             out_t = HA.t;
             cA = 1.0;
             const int pk = up ? k + 1 : k - 1;
@@ -485,7 +499,8 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
         }
     }
     if (!BACKWARD) {
-        if (!deferred && s == 0) {
+        // a nearer pass replaces only what it finds in front (a blend may land a little behind)
+        if (!deferred && s == 0 && (!S.nearer || (found && (float)out_t < clip))) {
             depth[p] = (float)out_t;
             hit[p] = hid;
         }
@@ -555,11 +570,11 @@ template <bool BACKWARD>
 __global__ __launch_bounds__(256, BACKWARD ? 4 : 6) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
                                                       const float* __restrict__ mip, float* __restrict__ depth,
                                                       int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                                      float* __restrict__ gtex, int* __restrict__ work)
+                                                      float* __restrict__ gtex, int* __restrict__ work, SurfaceArgs S)
 {
     const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
     const bool deferred = raycast_pixel<BACKWARD, 1>(A, col, row, tex, mip, depth, hit, gdepth, gtex, 0,
-                                                     work ? RAY_BUDGET : INT_MAX);
+                                                     work ? RAY_BUDGET : INT_MAX, S);
     if (!work) return;
     const uint64_t m = __ballot(deferred);  // one queue reservation per wave
     if (!m) return;
@@ -581,7 +596,8 @@ template <bool BACKWARD>
 __global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const float* __restrict__ tex,
                                                            const float* __restrict__ mip, float* __restrict__ depth,
                                                            int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                                           float* __restrict__ gtex, int* __restrict__ work)
+                                                           float* __restrict__ gtex, int* __restrict__ work,
+                                                           SurfaceArgs S)
 {
     constexpr int G = RAY_SPLIT, PER_WAVE = 64 / G;
     const int lane = __lane_id(), s = lane & (G - 1);
@@ -593,7 +609,7 @@ __global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const floa
         const bool has = idx < count;
         const int p = has ? work[2 + idx] : 0;
         raycast_pixel<BACKWARD, G>(A, has ? p % A.W : A.W, has ? p / A.W : 0, tex, mip, depth, hit, gdepth, gtex, s,
-                                   INT_MAX);
+                                   INT_MAX, S);
     }
 }
 
@@ -635,7 +651,7 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
             const int local = w - v_lo;
             const int tx = local % V.tiles_x, ty = local / V.tiles_x;
             raycast_pixel<BACKWARD, 1>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,
-                                       V.gdepth, V.gtex, 0, INT_MAX);
+                                       V.gdepth, V.gtex, 0, INT_MAX, SurfaceArgs{0, false, nullptr});
         }
     }
 }
@@ -689,16 +705,16 @@ namespace {
 // The frame kernel, then (with a workspace) the queue of long rays.
 template <bool BACKWARD>
 void launch_raycast(const RayArgs& A, const float* tex, const float* mip, float* depth, int32_t* hit,
-                    const float* gdepth, float* gtex, int32_t* work, hipStream_t s)
+                    const float* gdepth, float* gtex, int32_t* work, const SurfaceArgs& S, hipStream_t s)
 {
     if (work) zero_queue_kernel<<<1, 64, 0, s>>>(work);
     const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
-    raycast_kernel<BACKWARD><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work);
+    raycast_kernel<BACKWARD><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
     if (!work) return;
     // persistent: enough lane groups that a typical queue is taken in one round
     const int64_t pixels = (int64_t)A.W * A.H;
     const int blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(64, pixels / 1024));
-    raycast_tail_kernel<BACKWARD><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work);
+    raycast_tail_kernel<BACKWARD><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
 }
 
 }  // namespace
@@ -711,8 +727,25 @@ extern "C" hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, 
     hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
-    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, (hipStream_t)stream);
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr},
+                          (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast");
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_raycast_nearer(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                                         int32_t K, const float* tex, const float* mip, int32_t surface, float* depth,
+                                         int32_t* hit, int32_t* work, hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
+    HFR_REQUIRE(surface >= 1 && surface <= HFR_MAX_SURFACES - 1, "surface %d outside [1, %d]", surface,
+                HFR_MAX_SURFACES - 1);
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{surface, true, nullptr},
+                          (hipStream_t)stream);
+    HFR_LAUNCH_CHECK("raycast_nearer");
     return hfr_ok();
 }
 
@@ -724,8 +757,27 @@ extern "C" hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_doma
     hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && grad_depth && grad_tex, "NULL texture, mipmap or gradient");
-    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work, (hipStream_t)stream);
+    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work, SurfaceArgs{0, false, nullptr},
+                         (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_backward");
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_raycast_backward_surface(const hfr_camera* cam, const hfr_domain* dom,
+                                                   const hfr_cascade* cas, int32_t K, const float* tex,
+                                                   const float* mip, int32_t surface, const int32_t* hit,
+                                                   const float* grad_depth, float* grad_tex, int32_t* work,
+                                                   hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && hit && grad_depth && grad_tex, "NULL texture, mipmap, hit or gradient");
+    HFR_REQUIRE(surface >= 0 && surface <= HFR_MAX_SURFACES - 1, "surface %d outside [0, %d]", surface,
+                HFR_MAX_SURFACES - 1);
+    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work,
+                         SurfaceArgs{surface, false, hit}, (hipStream_t)stream);
+    HFR_LAUNCH_CHECK("raycast_backward_surface");
     return hfr_ok();
 }
 

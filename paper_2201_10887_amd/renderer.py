@@ -38,6 +38,7 @@ class Renderer:
         self.long_ray_queue = True
         self.long_ray_queue_backward = True
         self._work = {}
+        self.extra = []  # further surfaces on the same cells (add_surface)
 
     def ray_work(self, cam, backward: bool = False):
         """The long-ray queue for this camera's image size (None when disabled)."""
@@ -98,19 +99,64 @@ class Renderer:
     def refresh_leaves(self, stream=None):
         """Re-derive the packed leaf records after ``L.v`` or ``L.sigma`` changed."""
         api.pack_leaves(self.L, stream)
+        for surf in self.extra:
+            api.pack_leaves(surf["L"], stream)
+
+    def add_surface(self, v) -> int:
+        """A further heightfield on the same cells, e.g. terrain plus relative water depth (Section 2):
+        values ``v`` per leaf, its own textures and pyramids over the same cascades, drawn where it is
+        nearer.  Widens the domain's height range to cover it; returns the surface index."""
+        import torch
+        s = 1 + len(self.extra)
+        if s >= 4:
+            raise ValueError("at most four surfaces")
+        L = self.L.with_values(v)
+        api.pack_leaves(L)
+        d = self.dom
+        self.dom = api.domain(_Dom(d.x0, d.y0, d.x1, d.y1, min(d.zmin, float(np.min(v))), max(d.zmax, float(np.max(v)))))
+        K, N = self.K, self.N
+        self.extra.append({"L": L, "tex": torch.empty_like(self.tex), "mask": torch.empty_like(self.mask),
+                           "mip": torch.empty_like(self.mip), "grad_tex": torch.zeros_like(self.tex),
+                           "grad_v": torch.zeros(L.n, dtype=torch.float32, device=self.device)})
+        return s
+
+    def surfaces(self):
+        """(leaves, textures, masks, pyramids) of every surface, surface 0 first."""
+        yield self.L, self.tex, self.mask, self.mip
+        for surf in self.extra:
+            yield surf["L"], surf["tex"], surf["mask"], surf["mip"]
 
     def forward(self, cam, cascades=None, depth=None, hit=None, stream=None):
         cas = self.fit(cam) if cascades is None else cascades
-        api.discretize(self.L, self.dom, cas, self.tex, self.mask, stream)
-        api.build_maxmip(self.tex, self.mip, stream)
-        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream, self.ray_work(cam))
+        for L, tex, mask, mip in self.surfaces():
+            api.discretize(L, self.dom, cas, tex, mask, stream)
+            api.build_maxmip(tex, mip, stream)
+        work = self.ray_work(cam)
+        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream, work)
+        for s, surf in enumerate(self.extra, start=1):
+            api.raycast_nearer(cam, self.dom, cas, surf["tex"], surf["mip"], s, depth, hit, stream, work)
         return depth, hit, cas
 
-    def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None):
-        """Accumulates into the (caller-zeroed) gradient buffers."""
-        api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream,
-                             self.ray_work(cam, backward=True))
-        api.discretize_backward(self.L, self.dom, cascades, self.tex, grad_tex, grad_v, grad_sigma, stream)
+    def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None, hit=None):
+        """Accumulates into the (caller-zeroed) gradient buffers.  With several surfaces, ``hit`` (the
+        forward pass's) routes each pixel's gradient to the surface it shows: surface 0 into grad_tex and
+        grad_v, surface s into its own zeroed ``extra[s - 1]["grad_tex"]`` / ``["grad_v"]``; the widths
+        are shared, so grad_sigma sums over the surfaces."""
+        work = self.ray_work(cam, backward=True)
+        if not self.extra:
+            api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream, work)
+            api.discretize_backward(self.L, self.dom, cascades, self.tex, grad_tex, grad_v, grad_sigma, stream)
+            return grad_v, grad_sigma
+        if hit is None:
+            raise ValueError("several surfaces: pass the forward pass's hit buffer")
+        for s, (L, tex, _, mip) in enumerate(self.surfaces()):
+            gt = grad_tex if s == 0 else self.extra[s - 1]["grad_tex"]
+            gv = grad_v if s == 0 else self.extra[s - 1]["grad_v"]
+            if s > 0:
+                gt.zero_()
+                gv.zero_()
+            api.raycast_backward_surface(cam, self.dom, cascades, tex, mip, s, hit, grad_depth, gt, stream, work)
+            api.discretize_backward(L, self.dom, cascades, tex, gt, gv, grad_sigma, stream)
         return grad_v, grad_sigma
 
 

@@ -103,6 +103,31 @@ def fbm_dem(n: int, octaves: int, hurst: float, seed: int, zrange: float = 300.0
     return acc.astype(np.float32)
 
 
+def water_surface(leaves: dict, side: float, seed: int, wet_fraction: float = 0.3, relief: float = 4.0,
+                  dry_drop: float = 1.0, raster_n: int = 512, x0: float = 0.0, y0: float = 0.0) -> np.ndarray:
+    """Per-leaf value of a synthetic water surface on the terrain's own cells, ``float32[n]``.
+
+    Stands in for the relative water depths of a flood simulation on the same
+    adaptive grid: a seeded smooth flood level (four octaves of the fBm
+    generator on a ``raster_n^2`` lattice, ``relief`` metres of variation,
+    sampled bilinearly at the cell centres) is raised until about
+    ``wet_fraction`` of the cells lie below it.  A wet cell holds terrain
+    value plus relative depth (the level there); a dry cell holds its terrain
+    value minus ``dry_drop``, so that the terrain is the nearer surface."""
+    lvl = fbm_dem(raster_n, 4, 0.8, seed, zrange=relief).astype(np.float64)
+    gx = np.clip((np.asarray(leaves["x"], np.float64) - x0) / side * raster_n - 0.5, 0.0, raster_n - 1.0)
+    gy = np.clip((np.asarray(leaves["y"], np.float64) - y0) / side * raster_n - 0.5, 0.0, raster_n - 1.0)
+    i0 = np.minimum(gx.astype(np.int64), raster_n - 2)
+    j0 = np.minimum(gy.astype(np.int64), raster_n - 2)
+    fx, fy = gx - i0, gy - j0
+    level = ((lvl[j0, i0] * (1 - fx) + lvl[j0, i0 + 1] * fx) * (1 - fy)
+             + (lvl[j0 + 1, i0] * (1 - fx) + lvl[j0 + 1, i0 + 1] * fx) * fy)
+    v = np.asarray(leaves["v"], np.float64)
+    level += np.quantile(v - level, wet_fraction)
+    depth = level - v
+    return np.where(depth > 0.0, v + depth, v - dry_drop).astype(np.float32)
+
+
 @dataclasses.dataclass(frozen=True)
 class Camera:
     """Pinhole camera: world x east, y north, z up; yaw 0 looks along +y, pitch < 0 looks down."""
@@ -155,6 +180,8 @@ class Workload:
     overlap: float = 0.05  # overlap width as a fraction of the cascade depth range
     mountains: float = 0.0
     zrange: float = 300.0
+    water_seed: int = 0    # > 0: a second surface, water on the terrain's cells (water_surface)
+    water_wet: float = 0.3
 
     @property
     def c_min(self) -> float:
@@ -195,7 +222,11 @@ LARGE = Workload(name="large: 163.84 km fBm + ridged mountains, 64.1M leaves (de
               pitch_deg=-3.0, vfov_deg=60.0, width=3840, height=2160, cascades=4, tex_n=4096,
               split_lambda=0.5, mountains=1500.0)
 
-WORKLOADS = {"tiny": TINY, "medium": MEDIUM, "paper": PAPER, "large": LARGE}
+MEDIUM_WATER = dataclasses.replace(
+    MEDIUM, name="medium + water: the 40.96 km scene with a flood surface on 30 % of its cells (two surfaces), "
+                 "4x2048^2 cascades each, 1920x1080", water_seed=91)
+
+WORKLOADS = {"tiny": TINY, "medium": MEDIUM, "paper": PAPER, "large": LARGE, "medium_water": MEDIUM_WATER}
 
 
 def domain_of(w: Workload, dem: np.ndarray) -> Domain:
