@@ -56,12 +56,38 @@ def build_scene(name: str):
     # rasters above 4096^2 take minutes in NumPy; the same generator runs in torch on the GPU
     dev = "cuda" if w.dem_n > 4096 else None
     dem = synth.fbm_dem(w.dem_n, w.octaves, w.hurst, w.seed, mountains=w.mountains, device=dev)
+    t1 = time.perf_counter()
     leaves = api.build_quadtree(dem, w.side, w.max_depth, w.tau)
+    build_scene.quadtree_host_ms = (time.perf_counter() - t1) * 1e3
     leaves["sigma"] = np.full(len(leaves["x"]), w.sigma, np.float32)
     cam = synth.camera_of(w, dem)
     print(f"[bench] scene {name}: {len(leaves['x'])} leaves, built in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
     return w, dem, leaves, cam
+
+
+def startup_ms(R, dem, w) -> dict:
+    """Start-up costs: the quadtree on the host and on the device (the raster already resident,
+    the leaf count read back once), and the host level index."""
+    import torch
+    from paper_2201_10887_amd import api
+    d = torch.as_tensor(np.ascontiguousarray(dem, np.float32), device="cuda")
+    api.build_quadtree_device(d, w.side, w.max_depth, w.tau)  # first call: allocator warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q = api.build_quadtree_device(d, w.side, w.max_depth, w.tau)
+    torch.cuda.synchronize()
+    t_dev = (time.perf_counter() - t0) * 1e3
+    if q["x"].numel() != R.L.n:
+        raise RuntimeError("device and host quadtrees differ in leaf count")
+    del q, d
+    leaves = {"x": R.L.x.cpu().numpy(), "y": R.L.y.cpu().numpy(), "c": R.L.c.cpu().numpy()}
+    t0 = time.perf_counter()
+    api.build_level_index(leaves, w.side, w.max_depth)
+    t_index = (time.perf_counter() - t0) * 1e3
+    torch.cuda.empty_cache()
+    return {"quadtree_host": round(build_scene.quadtree_host_ms, 1), "quadtree_device": round(t_dev, 2),
+            "level_index_host": round(t_index, 1)}
 
 
 def timed(fn, steps, stream):
@@ -423,6 +449,7 @@ def main():
         R.fit(cam)
     fit_us = (time.perf_counter() - t_host) * 1e4
 
+    startup = startup_ms(R, dem, w)
     work = discretize_work(R, cas, leaves, w)
     vis_texels, pairs = work["visible_texels"], work["pairs"]
     forward()  # leave the full frame (every surface) in depth / hit
@@ -471,6 +498,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "long_ray_queue": {"forward": R.long_ray_queue, "adjoint": R.long_ray_queue_backward, "tuning_ms": tuned},
         "fit_cascades_host_us": round(fit_us, 1),
+        "startup_ms": startup,
         "gtexel_per_s": round(vis_texels / (stage_ms["discretize"] * 1e-3) / 1e9, 3),
         "gtexel_per_s_all": round(K * R.N * R.N / (stage_ms["discretize"] * 1e-3) / 1e9, 3),
         "grays_per_s": round(W * H / (stage_ms["raycast"] * 1e-3) / 1e9, 3),

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 6
+#define HFR_ABI_VERSION 7
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -173,6 +173,29 @@ hfr_status hfr_neighbours_size(const hfr_neighbours* nb, int64_t* nnz);
 /* Writes host off[n + 1] (CSR offsets) and idx[nnz] (leaf indices). */
 hfr_status hfr_neighbours_export(const hfr_neighbours* nb, int32_t* off, int32_t* idx);
 void hfr_neighbours_destroy(hfr_neighbours* nb);
+
+/* The same quadtree built on the device (Section 2's adaptive grid, which the
+ * paper builds at start-up; on the device it can follow a raster that changes,
+ * such as simulation output).  Decisions are hfr_build_quadtree's, in the same
+ * FP64 arithmetic, so the leaves are the same set; they come out sorted by
+ * (level, row, column), i.e. already in level-index order (order = 0 .. n-1).
+ * Two calls: hfr_build_quadtree_device classifies every lattice node, writes
+ * the level index (rank, as hfr_build_level_index) and returns the leaf count
+ * (it synchronizes the stream to read it); hfr_quadtree_device_leaves then
+ * writes the leaves.  dem: device float[n][n], n a power of two <= 32768.
+ * work: device scratch of hfr_quadtree_device_workspace bytes (the FP64 mean
+ * pyramid and flags; read again by the second call).  rank: device
+ * int32[(4^(max_depth+1) - 1) / 3 + max_depth + 1].  x, y, c, v: device
+ * float[n_leaves]; level, i, j: device int32[n_leaves] or NULL.  EINVAL: as
+ * hfr_build_quadtree, max_depth > 15, NULL pointers. */
+hfr_status hfr_quadtree_device_workspace(int64_t n, int32_t max_depth, int64_t* bytes);
+hfr_status hfr_build_quadtree_device(const float* dem, int64_t n, double side, double x0, double y0,
+                                     int32_t max_depth, double tau, void* work, int32_t* rank,
+                                     int64_t* n_leaves, hfr_stream stream);
+hfr_status hfr_quadtree_device_leaves(int64_t n, double side, double x0, double y0, int32_t max_depth,
+                                      const void* work, const int32_t* rank, int64_t n_leaves, float* x,
+                                      float* y, float* c, float* v, int32_t* level, int32_t* i, int32_t* j,
+                                      hfr_stream stream);
 
 /* Level index of the leaves (host arrays).  Leaves are ordered by level,
  * then lattice row j (y), then column i (x): order[p] is the leaf at sorted

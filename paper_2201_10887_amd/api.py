@@ -116,6 +116,35 @@ def build_quadtree(dem: np.ndarray, side: float, max_depth: int, tau: float, x0:
     return out
 
 
+def build_quadtree_device(dem, side: float, max_depth: int, tau: float, x0: float = 0.0, y0: float = 0.0,
+                          stream=None) -> dict:
+    """The quadtree built on the device from a device raster (torch tensor, float32 [n][n]).
+
+    Returns device tensors ``x, y, c, v`` (float32) and ``level, i, j`` (int32), sorted by (level, row,
+    column), with their level index ``rank`` and ``order`` (0 .. n-1): ``(rank, order)`` is what
+    ``DeviceLeaves.from_device`` takes."""
+    import torch
+    n = int(dem.shape[0])
+    if dem.dim() != 2 or dem.shape[1] != n:
+        raise ValueError("raster must be square")
+    _dev(dem, torch.float32, (n, n), "dem")
+    nbytes = ctypes.c_int64()
+    call("hfr_quadtree_device_workspace", n, max_depth, ctypes.byref(nbytes))
+    work = torch.empty(nbytes.value, dtype=torch.uint8, device=dem.device)
+    rank = torch.empty(rank_table_size(max_depth), dtype=torch.int32, device=dem.device)
+    count = ctypes.c_int64()
+    call("hfr_build_quadtree_device", dem.data_ptr(), n, side, x0, y0, max_depth, tau, work.data_ptr(),
+         rank.data_ptr(), ctypes.byref(count), _stream(stream))
+    m = count.value
+    out = {k: torch.empty(m, dtype=torch.float32, device=dem.device) for k in ("x", "y", "c", "v")}
+    out.update({k: torch.empty(m, dtype=torch.int32, device=dem.device) for k in ("level", "i", "j")})
+    call("hfr_quadtree_device_leaves", n, side, x0, y0, max_depth, work.data_ptr(), rank.data_ptr(), m,
+         *(out[k].data_ptr() for k in ("x", "y", "c", "v", "level", "i", "j")), _stream(stream))
+    out["rank"] = rank
+    out["order"] = torch.arange(m, dtype=torch.int32, device=dem.device)
+    return out
+
+
 def quadtree_leaf_count(dem: np.ndarray, side: float, max_depth: int, tau: float) -> int:
     """Leaf count of ``build_quadtree`` without exporting the leaves."""
     dem = np.ascontiguousarray(dem, np.float32)
@@ -194,6 +223,27 @@ class DeviceLeaves:
         self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=device)
         self.max_depth, self.cutoff = int(max_depth), float(cutoff)
         self.x0, self.y0, self.side = float(x0), float(y0), float(side)
+
+    @classmethod
+    def from_device(cls, leaves: dict, sigma, side: float, max_depth: int, cutoff: float, x0: float = 0.0,
+                    y0: float = 0.0) -> "DeviceLeaves":
+        """From ``build_quadtree_device`` output (device tensors, level index included) and widths
+        ``sigma`` (a device tensor or a scalar); nothing goes through the host."""
+        import torch
+        self = object.__new__(cls)
+        dev = leaves["x"].device
+        self.x, self.y, self.c, self.v = (leaves[k].contiguous() for k in ("x", "y", "c", "v"))
+        self.n = int(self.x.numel())
+        self.sigma = (sigma.to(dev, torch.float32).contiguous() if torch.is_tensor(sigma)
+                      else torch.full((self.n,), float(sigma), dtype=torch.float32, device=dev))
+        self.rank, self.order = leaves["rank"], leaves["order"]
+        if self.rank.numel() != rank_table_size(max_depth):
+            raise ValueError("level index does not match max_depth")
+        self.packed = torch.empty((self.n, 4), dtype=torch.float32, device=dev)
+        self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=dev)
+        self.max_depth, self.cutoff = int(max_depth), float(cutoff)
+        self.x0, self.y0, self.side = float(x0), float(y0), float(side)
+        return self
 
     def with_values(self, v) -> "DeviceLeaves":
         """Another heightfield on the same cells (shares positions, sizes, widths and the level index):

@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["hfr_host.cpp"]
-DEVICE_SOURCES = ["hfr_discretize.hip", "hfr_maxmip.hip", "hfr_raycast.hip", "hfr_batch.hip"]
+DEVICE_SOURCES = ["hfr_discretize.hip", "hfr_maxmip.hip", "hfr_raycast.hip", "hfr_batch.hip", "hfr_quadtree.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics"]

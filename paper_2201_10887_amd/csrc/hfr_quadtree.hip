@@ -1,0 +1,296 @@
+// Adaptive quadtree of a raster built on the device (the adaptive grid of
+// Section 2, built at start-up in the paper), producing the leaves directly
+// in level-index order together with their rank table.  gfx950, wave64.
+//
+// The decisions are those of hfr_build_quadtree, made with the same FP64
+// arithmetic: a mean pyramid of 2 x 2 averages ((a + b) + (c + d)) / 4, and a
+// node splits (below max_depth) when the largest |second difference| of its
+// four children's means (neighbours replicated at the raster edge) exceeds
+// tau.  Instead of a depth-first walk every lattice node is classified at
+// once, level after level: a node is present when its parent is present and
+// splits, and a leaf when it is present and does not split.  The leaf flags,
+// written one slot late into the rank-table layout with a 0 opening every
+// level, become the rank table under one inclusive scan; each leaf is then
+// written at its rank, so the leaves come out sorted by (level, row, column).
+#include <algorithm>
+
+#include "hfr_device.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+inline int64_t pyramid_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+inline int64_t rank_offset(int l) { return pyramid_offset(l) + l; }
+
+__global__ void raster_to_double_kernel(const float* __restrict__ dem, double* __restrict__ out, int64_t count)
+{
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < count; a += (int64_t)gridDim.x * blockDim.x)
+        out[a] = (double)dem[a];
+}
+
+// Level of side s from the level of side 2s below it.
+__global__ void mean_level_kernel(const double* __restrict__ fine, double* __restrict__ coarse, int s)
+{
+    const int64_t count = (int64_t)s * s;
+    const int64_t s2 = 2 * (int64_t)s;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < count; a += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t jj = a / s, ii = a - jj * s;
+        const double p = fine[(2 * jj) * s2 + 2 * ii], q = fine[(2 * jj) * s2 + 2 * ii + 1];
+        const double r = fine[(2 * jj + 1) * s2 + 2 * ii], t = fine[(2 * jj + 1) * s2 + 2 * ii + 1];
+        coarse[a] = __dmul_rn(__dadd_rn(__dadd_rn(p, q), __dadd_rn(r, t)), 0.25);
+    }
+}
+
+// split[q] for the nodes of a level of side s, from the means of the level below (side 2s).
+__global__ void split_kernel(const double* __restrict__ m, int s, double tau, uint8_t* __restrict__ split)
+{
+    const int64_t count = (int64_t)s * s;
+    const int64_t S = 2 * (int64_t)s;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < count; a += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t jj = a / s, ii = a - jj * s;
+        double best = 0.0;
+        for (int64_t cj = 2 * jj; cj <= 2 * jj + 1; ++cj)
+            for (int64_t ci = 2 * ii; ci <= 2 * ii + 1; ++ci) {
+                const double ctr = m[cj * S + ci];
+                const double lf = m[cj * S + (ci > 0 ? ci - 1 : 0)];
+                const double rt = m[cj * S + (ci + 1 < S ? ci + 1 : S - 1)];
+                const double dn = m[(cj > 0 ? cj - 1 : 0) * S + ci];
+                const double up = m[(cj + 1 < S ? cj + 1 : S - 1) * S + ci];
+                // 2 ctr is exact, so a fused subtract rounds like the separate one
+                const double d2x = __dsub_rn(__dadd_rn(lf, rt), __dmul_rn(2.0, ctr));
+                const double d2y = __dsub_rn(__dadd_rn(dn, up), __dmul_rn(2.0, ctr));
+                best = fmax(best, fmax(fabs(d2x), fabs(d2y)));
+            }
+        split[a] = best > tau ? 1 : 0;
+    }
+}
+
+// Presence and leaf flags of level l (side s): flags go to rank[off_l + q + 1],
+// with rank[off_l] = 0 opening the level.
+__global__ void leaf_flags_kernel(int l, int max_depth, const uint8_t* __restrict__ split_l,
+                                  const uint8_t* __restrict__ present_up, const uint8_t* __restrict__ split_up,
+                                  uint8_t* __restrict__ present_l, int32_t* __restrict__ rank_l)
+{
+    const int s = 1 << l;
+    const int64_t count = (int64_t)s * s;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < count; a += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t jj = a >> l, ii = a & (s - 1);
+        bool present = true;
+        if (l > 0) {
+            const int64_t pq = (jj >> 1) * (s >> 1) + (ii >> 1);
+            present = present_up[pq] && split_up[pq];
+        }
+        const bool splits = l < max_depth && split_l[a];
+        present_l[a] = present ? 1 : 0;
+        rank_l[a + 1] = (present && !splits) ? 1 : 0;
+        if (a == 0) rank_l[0] = 0;
+    }
+}
+
+// In-place inclusive scan of each SCAN_TILE-element tile; the tile's total
+// goes to sums[tile].
+__global__ __launch_bounds__(SCAN_THREADS) void scan_tiles_kernel(int32_t* __restrict__ data, int64_t n,
+                                                                  int32_t* __restrict__ sums)
+{
+    __shared__ int32_t buf[SCAN_TILE];
+    __shared__ int32_t wsum[SCAN_THREADS / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int e = k * SCAN_THREADS + t;
+        buf[e] = base + e < n ? data[base + e] : 0;
+    }
+    __syncthreads();
+    int32_t run = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        run += buf[t * SCAN_ITEMS + k];
+        buf[t * SCAN_ITEMS + k] = run;
+    }
+    int32_t incl = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int32_t before = incl - run;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    for (int k = 0; k < SCAN_ITEMS; ++k) buf[t * SCAN_ITEMS + k] += before;
+    __syncthreads();
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int e = k * SCAN_THREADS + t;
+        if (base + e < n) data[base + e] = buf[e];
+    }
+    if (t == SCAN_THREADS - 1) sums[blockIdx.x] = buf[SCAN_TILE - 1];
+}
+
+// Adds the inclusive prefix of the earlier tiles' totals to every tile but the first.
+__global__ void add_tile_offsets_kernel(int32_t* __restrict__ data, int64_t n, const int32_t* __restrict__ sums)
+{
+    const int64_t tile = (int64_t)blockIdx.x + 1;
+    const int32_t add = sums[tile - 1];
+    for (int64_t e = tile * SCAN_TILE + threadIdx.x; e < std::min<int64_t>(n, (tile + 1) * SCAN_TILE);
+         e += blockDim.x)
+        data[e] += add;
+}
+
+// Leaves of level l written at their ranks.
+__global__ void emit_leaves_kernel(int l, double side, double x0, double y0, const double* __restrict__ mean_l,
+                                   const int32_t* __restrict__ rank_l, float* __restrict__ x, float* __restrict__ y,
+                                   float* __restrict__ c, float* __restrict__ v, int32_t* __restrict__ level,
+                                   int32_t* __restrict__ li, int32_t* __restrict__ lj, int64_t n_leaves)
+{
+    const int s = 1 << l;
+    const int64_t count = (int64_t)s * s;
+    const double cs = ldexp(side, -l);
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < count; a += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = rank_l[a];
+        if (rank_l[a + 1] - p != 1 || p < 0 || p >= n_leaves) continue;
+        const int64_t jj = a >> l, ii = a & (s - 1);
+        x[p] = (float)__dadd_rn(x0, __dmul_rn((double)ii + 0.5, cs));
+        y[p] = (float)__dadd_rn(y0, __dmul_rn((double)jj + 0.5, cs));
+        c[p] = (float)cs;
+        v[p] = (float)mean_l[a];
+        if (level) level[p] = l;
+        if (li) li[p] = (int32_t)ii;
+        if (lj) lj[p] = (int32_t)jj;
+    }
+}
+
+struct Layout {
+    int64_t pyramid;  // double, levels 0 .. D
+    int64_t split;    // uint8, levels 0 .. max_depth - 1
+    int64_t present;  // uint8, levels 0 .. max_depth
+    int64_t sums;     // int32, the scan's tile totals, every recursion level
+    int64_t bytes;
+};
+
+int64_t scan_sums_count(int64_t n)
+{
+    int64_t total = 0;
+    while (n > 1) {
+        n = (n + SCAN_TILE - 1) / SCAN_TILE;
+        total += n;
+    }
+    return total + 1;
+}
+
+Layout layout_of(int D, int max_depth)
+{
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    Layout L{};
+    L.pyramid = 0;
+    L.split = up(L.pyramid + pyramid_offset(D + 1) * 8);
+    L.present = up(L.split + pyramid_offset(max_depth));
+    L.sums = up(L.present + pyramid_offset(max_depth + 1));
+    L.bytes = up(L.sums + scan_sums_count(rank_offset(max_depth + 1)) * 4);
+    return L;
+}
+
+int grid_for(int64_t count) { return (int)std::min<int64_t>((count + 255) / 256, 8192); }
+
+// Inclusive scan of data[0, n) in place; sums has scan_sums_count(n) entries.
+void scan_inclusive(int32_t* data, int64_t n, int32_t* sums, hipStream_t s)
+{
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    scan_tiles_kernel<<<dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s>>>(data, n, sums);
+    if (tiles > 1) {
+        scan_inclusive(sums, tiles, sums + tiles, s);
+        add_tile_offsets_kernel<<<dim3((unsigned)(tiles - 1)), dim3(256), 0, s>>>(data, n, sums);
+    }
+}
+
+hfr_status check_args(int64_t n, double side, double x0, double y0, int32_t max_depth, int* D)
+{
+    HFR_REQUIRE(hfr_is_pow2(n) && n <= 32768, "raster side %lld must be a power of two <= 32768", (long long)n);
+    *D = hfr_log2i(n);
+    HFR_REQUIRE(max_depth >= 0 && max_depth <= *D && max_depth <= 15, "max_depth %d outside [0, min(%d, 15)]",
+                max_depth, *D);
+    HFR_REQUIRE(std::isfinite(side) && side > 0 && std::isfinite(x0) && std::isfinite(y0),
+                "side must be positive and the origin finite");
+    return HFR_OK;
+}
+
+}  // namespace
+
+extern "C" hfr_status hfr_quadtree_device_workspace(int64_t n, int32_t max_depth, int64_t* bytes)
+{
+    HFR_REQUIRE(bytes != nullptr, "bytes is NULL");
+    int D = 0;
+    hfr_status st = check_args(n, 1.0, 0.0, 0.0, max_depth, &D);
+    if (st != HFR_OK) return st;
+    *bytes = layout_of(D, max_depth).bytes;
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_build_quadtree_device(const float* dem, int64_t n, double side, double x0, double y0,
+                                                int32_t max_depth, double tau, void* work, int32_t* rank,
+                                                int64_t* n_leaves, hfr_stream stream)
+{
+    HFR_REQUIRE(dem && work && rank && n_leaves, "NULL raster, workspace, rank table or count");
+    HFR_REQUIRE(!std::isnan(tau), "tau is NaN");
+    int D = 0;
+    hfr_status st = check_args(n, side, x0, y0, max_depth, &D);
+    if (st != HFR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const Layout lay = layout_of(D, max_depth);
+    char* w = static_cast<char*>(work);
+    double* pyr = reinterpret_cast<double*>(w + lay.pyramid);
+    uint8_t* split = reinterpret_cast<uint8_t*>(w + lay.split);
+    uint8_t* present = reinterpret_cast<uint8_t*>(w + lay.present);
+    int32_t* sums = reinterpret_cast<int32_t*>(w + lay.sums);
+    raster_to_double_kernel<<<grid_for(n * n), 256, 0, s>>>(dem, pyr + pyramid_offset(D), n * n);
+    for (int l = D - 1; l >= 0; --l) {
+        const int64_t side_l = int64_t(1) << l;
+        mean_level_kernel<<<grid_for(side_l * side_l), 256, 0, s>>>(pyr + pyramid_offset(l + 1),
+                                                                      pyr + pyramid_offset(l), (int)side_l);
+    }
+    for (int l = 0; l < max_depth; ++l) {
+        const int64_t side_l = int64_t(1) << l;
+        split_kernel<<<grid_for(side_l * side_l), 256, 0, s>>>(pyr + pyramid_offset(l + 1), (int)side_l, tau,
+                                                                 split + pyramid_offset(l));
+    }
+    for (int l = 0; l <= max_depth; ++l) {
+        const int64_t side_l = int64_t(1) << l;
+        leaf_flags_kernel<<<grid_for(side_l * side_l), 256, 0, s>>>(
+            l, max_depth, l < max_depth ? split + pyramid_offset(l) : nullptr,
+            l > 0 ? present + pyramid_offset(l - 1) : nullptr, l > 0 ? split + pyramid_offset(l - 1) : nullptr,
+            present + pyramid_offset(l), rank + rank_offset(l));
+    }
+    const int64_t total = rank_offset(max_depth + 1);
+    scan_inclusive(rank, total, sums, s);
+    HFR_LAUNCH_CHECK("build_quadtree_device");
+    int32_t count = 0;
+    HFR_REQUIRE(hipMemcpyAsync(&count, rank + total - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess,
+                "reading the leaf count failed");
+    *n_leaves = count;
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_quadtree_device_leaves(int64_t n, double side, double x0, double y0, int32_t max_depth,
+                                                 const void* work, const int32_t* rank, int64_t n_leaves, float* x,
+                                                 float* y, float* c, float* v, int32_t* level, int32_t* i, int32_t* j,
+                                                 hfr_stream stream)
+{
+    HFR_REQUIRE(work && rank && x && y && c && v, "NULL workspace, rank table or leaf array");
+    HFR_REQUIRE(n_leaves >= 1 && n_leaves <= INT32_MAX, "leaf count %lld outside [1, INT32_MAX]",
+                (long long)n_leaves);
+    int D = 0;
+    hfr_status st = check_args(n, side, x0, y0, max_depth, &D);
+    if (st != HFR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const Layout lay = layout_of(D, max_depth);
+    const double* pyr = reinterpret_cast<const double*>(static_cast<const char*>(work) + lay.pyramid);
+    for (int l = 0; l <= max_depth; ++l) {
+        const int64_t side_l = int64_t(1) << l;
+        emit_leaves_kernel<<<grid_for(side_l * side_l), 256, 0, s>>>(l, side, x0, y0, pyr + pyramid_offset(l),
+                                                                       rank + rank_offset(l), x, y, c, v, level, i, j,
+                                                                       n_leaves);
+    }
+    HFR_LAUNCH_CHECK("quadtree_device_leaves");
+    return hfr_ok();
+}

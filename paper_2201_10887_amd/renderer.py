@@ -20,13 +20,33 @@ class Renderer:
     def __init__(self, leaves: dict, side: float, max_depth: int, cutoff: float, cascades: int, tex_n: int,
                  split_lambda: float, overlap: float, device: str = "cuda",
                  x0: float = 0.0, y0: float = 0.0):
-        import torch
-        self.side, self.max_depth, self.cutoff = float(side), int(max_depth), float(cutoff)
-        self.K, self.N, self.lam, self.overlap = int(cascades), int(tex_n), float(split_lambda), float(overlap)
-        self.c_min = float(np.min(leaves["c"]))
-        self.dom = api.domain(_Dom(x0, y0, x0 + side, y0 + side, float(np.min(leaves["v"])), float(np.max(leaves["v"]))))
         index = api.build_level_index(leaves, side, max_depth, x0, y0)
-        self.L = api.DeviceLeaves(leaves, index, side, max_depth, cutoff, x0, y0, device=device)
+        L = api.DeviceLeaves(leaves, index, side, max_depth, cutoff, x0, y0, device=device)
+        self._setup(L, float(np.min(leaves["c"])), float(np.min(leaves["v"])), float(np.max(leaves["v"])),
+                    cascades, tex_n, split_lambda, overlap, device)
+
+    @classmethod
+    def from_raster(cls, dem, side: float, max_depth: int, tau: float, sigma, cutoff: float, cascades: int,
+                    tex_n: int, split_lambda: float, overlap: float, x0: float = 0.0, y0: float = 0.0) -> "Renderer":
+        """The whole start-up on the device from a device raster (float32 [n][n] tensor): the quadtree
+        and its level index (build_quadtree_device) and the packed records.  Only the leaf count, the
+        smallest cell and the value range come back to the host.  ``sigma``: widths per leaf (tensor,
+        in leaf order) or one width for all."""
+        import torch
+        q = api.build_quadtree_device(dem, side, max_depth, tau, x0, y0)
+        L = api.DeviceLeaves.from_device(q, sigma, side, max_depth, cutoff, x0, y0)
+        c_min, v_min, v_max = torch.stack([L.c.min(), L.v.min(), L.v.max()]).tolist()
+        self = object.__new__(cls)
+        self._setup(L, c_min, v_min, v_max, cascades, tex_n, split_lambda, overlap, str(dem.device))
+        return self
+
+    def _setup(self, L, c_min, v_min, v_max, cascades, tex_n, split_lambda, overlap, device):
+        import torch
+        self.side, self.max_depth, self.cutoff = L.side, L.max_depth, L.cutoff
+        self.K, self.N, self.lam, self.overlap = int(cascades), int(tex_n), float(split_lambda), float(overlap)
+        self.c_min = float(c_min)
+        self.dom = api.domain(_Dom(L.x0, L.y0, L.x0 + L.side, L.y0 + L.side, float(v_min), float(v_max)))
+        self.L = L
         api.pack_leaves(self.L)
         K, N = self.K, self.N
         self.tex = torch.empty((K, N, N), dtype=torch.float32, device=device)

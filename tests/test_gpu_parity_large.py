@@ -64,6 +64,15 @@ def test_library_quadtree_matches_at_full_size(large):
         assert np.array_equal(got[k], large["leaves"][k]), k
 
 
+def test_device_quadtree_equals_oracle_at_full_size(gpu, large):
+    w = large["w"]
+    dev = api.build_quadtree_device(gpu.as_tensor(large["dem"], device="cuda"), w.side, w.max_depth, w.tau)
+    lv = large["leaves"]
+    order = np.lexsort((lv["i"], lv["j"], lv["level"]))
+    for k in ("x", "y", "c", "v", "level", "i", "j"):
+        assert np.array_equal(dev[k].cpu().numpy(), lv[k][order]), k
+
+
 def _reaching(leaves, cutoff, box):
     """Indices of every leaf whose truncation radius reaches the closed box (exact test, FP64)."""
     x = leaves["x"].astype(np.float64)
