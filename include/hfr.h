@@ -187,7 +187,10 @@ void hfr_neighbours_destroy(hfr_neighbours* nb);
  * pyramid and flags; read again by the second call).  rank: device
  * int32[(4^(max_depth+1) - 1) / 3 + max_depth + 1].  x, y, c, v: device
  * float[n_leaves]; level, i, j: device int32[n_leaves] or NULL.  EINVAL: as
- * hfr_build_quadtree, max_depth > 15, NULL pointers. */
+ * hfr_build_quadtree's argument checks, max_depth > 15, NULL pointers; the
+ * samples themselves are not checked on the device (a non-finite sample makes
+ * the means above it NaN, and a NaN criterion never splits).  The caller
+ * owns every buffer. */
 hfr_status hfr_quadtree_device_workspace(int64_t n, int32_t max_depth, int64_t* bytes);
 hfr_status hfr_build_quadtree_device(const float* dem, int64_t n, double side, double x0, double y0,
                                      int32_t max_depth, double tau, void* work, int32_t* rank,

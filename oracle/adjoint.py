@@ -15,7 +15,8 @@ definitions in this oracle:
 * Eq. 2 w.r.t. leaf values and widths: ``dv_s/dv_j = w_j / S0`` and
   ``dv_s/dsigma_j = (v_j - v_s) / S0 * dw_j/dsigma_j`` with
   ``dw_j/dsigma_j = exp(-q^2/2) q^2 / sigma_j``, ``q = r / (sigma_j c_j)``;
-  the truncation constant does not depend on sigma.
+  the truncation constant does not depend on sigma.  With the Wendland basis
+  ``w = (1 - u)^4 (4u + 1)``, ``u = q / k``: ``dw_j/dsigma_j = 20 u^2 (1 - u)^3 / sigma_j``.
 * Central finite differences of the whole oracle pipeline for the checks.
 
 Pinned by ``tests/test_oracle_adjoint.py``: finite differences, the
@@ -28,7 +29,7 @@ import math
 
 import numpy as np
 
-from .discretize import clamp_to_domain, texel_centres
+from .discretize import basis_dweight_dsigma, clamp_to_domain, texel_centres
 
 
 def texel_gradients(res: dict, grad_depth: np.ndarray, K: int, N: int) -> np.ndarray:
@@ -62,8 +63,8 @@ def leaf_gradients(cascades, field, dom, gtex: np.ndarray) -> tuple:
         val, s0, (pi, lj, w) = field.evaluate(p, return_terms=True)
         gv += np.bincount(lj, weights=gsx[pi] * w / s0[pi], minlength=len(gv))
         r = np.hypot(L["x"][lj] - p[pi, 0], L["y"][lj] - p[pi, 1])
-        q2 = (r / (L["sigma"][lj] * L["c"][lj])) ** 2
-        dw = np.exp(-0.5 * q2) * q2 / L["sigma"][lj]
+        q = r / (L["sigma"][lj] * L["c"][lj])
+        dw = basis_dweight_dsigma(q, L["sigma"][lj], field.cutoff, getattr(field, "basis", "gaussian"))
         gs += np.bincount(lj, weights=gsx[pi] * (L["v"][lj] - val[pi]) / s0[pi] * dw, minlength=len(gs))
     return gv, gs
 

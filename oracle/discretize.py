@@ -11,10 +11,18 @@
   with the paper's ``k = 3.5``; here ``sigma`` may differ per leaf and ``k``
   is a parameter.  Leaf ``j`` influences ``p`` iff ``w_j(p) > 0``.
 * Eq. 2: ``v(p) = sum_j w_j v_j / sum_j w_j`` over the influencing leaves.
+* Another basis in Eq. 2's place of Eq. 1 (the two-step design admits any
+  reconstruction, Section 1 and Section 7): Wendland's compactly supported
+  C2 function ``phi(u) = (1 - u)^4 (4u + 1)`` for ``u < 1``, 0 beyond, with
+  ``u = |p_j - p| / (k sigma_j c_j)`` -- the same support radius as the
+  truncated Gaussian, so the same leaves influence the same points.
 * A visible texel whose centre lies outside the domain is evaluated at the
   centre clamped into the domain (reading; the paper is silent).
 
-Pinned by ``tests/test_oracle_discretize.py``: brute force over all leaves
+Pinned by ``tests/test_oracle_discretize.py`` (both bases where it applies,
+and ``tests/test_oracle_basis.py`` for the Wendland function: its integral
+over the plane, its value and derivatives at 0 and at the support edge, the
+derivative in sigma by finite differences): brute force over all leaves
 equals the range-query sum to 1e-12; a tilted plane on a uniform grid is
 reproduced exactly (symmetric neighbourhoods cancel first moments); the
 result stays within the influencing values; the truncated sum stays within
@@ -72,11 +80,36 @@ def texel_centres(cas, i: np.ndarray, j: np.ndarray) -> np.ndarray:
 
 # ---------------------------------------------------------------- Eq. 1 / Eq. 2
 
-def weights(p: np.ndarray, xj, yj, cj, sj, cutoff: float) -> np.ndarray:
-    """Eq. 1 for points ``p (m, 2)`` against leaves ``j`` (broadcast ``(m, L)``), clipped at 0."""
+BASES = ("gaussian", "wendland")
+
+
+def basis_weight(q: np.ndarray, cutoff: float, basis: str = "gaussian") -> np.ndarray:
+    """Weight at ``q = r / (sigma c)`` (unclipped for the Gaussian: Eq. 1 may go negative)."""
+    if basis == "gaussian":
+        return np.exp(-0.5 * q * q) - math.exp(-0.5 * cutoff * cutoff)
+    if basis == "wendland":
+        u = q / cutoff
+        return np.where(u < 1.0, (1.0 - u) ** 4 * (4.0 * u + 1.0), 0.0)
+    raise ValueError(f"unknown basis {basis!r}")
+
+
+def basis_dweight_dsigma(q: np.ndarray, sigma: np.ndarray, cutoff: float, basis: str = "gaussian") -> np.ndarray:
+    """``d w / d sigma`` at ``q = r / (sigma c)`` (q itself scales as 1 / sigma)."""
+    if basis == "gaussian":
+        return np.exp(-0.5 * q * q) * q * q / sigma
+    if basis == "wendland":
+        # w = (1 - u)^4 (4u + 1): dw/du = -20 u (1 - u)^3, du/dsigma = -u / sigma
+        u = q / cutoff
+        return np.where(u < 1.0, 20.0 * u * u * (1.0 - u) ** 3 / sigma, 0.0)
+    raise ValueError(f"unknown basis {basis!r}")
+
+
+def weights(p: np.ndarray, xj, yj, cj, sj, cutoff: float, basis: str = "gaussian") -> np.ndarray:
+    """Eq. 1 (or the other basis) for points ``p (m, 2)`` against leaves ``j`` (broadcast ``(m, L)``),
+    clipped at 0."""
     r = np.hypot(np.asarray(xj, np.float64)[None, :] - p[:, 0:1], np.asarray(yj, np.float64)[None, :] - p[:, 1:2])
     q = r / (np.asarray(sj, np.float64)[None, :] * np.asarray(cj, np.float64)[None, :])
-    w = np.exp(-0.5 * q * q) - math.exp(-0.5 * cutoff * cutoff)
+    w = basis_weight(q, cutoff, basis)
     return np.where(w > 0.0, w, 0.0)
 
 
@@ -84,12 +117,12 @@ def clamp_to_domain(p: np.ndarray, dom) -> np.ndarray:
     return np.stack([np.clip(p[:, 0], dom.x0, dom.x1), np.clip(p[:, 1], dom.y0, dom.y1)], axis=-1)
 
 
-def rbf_bruteforce(p: np.ndarray, leaves: dict, cutoff: float, chunk: int = 2048) -> tuple:
+def rbf_bruteforce(p: np.ndarray, leaves: dict, cutoff: float, chunk: int = 2048, basis: str = "gaussian") -> tuple:
     """Eq. 2 at points ``p`` summing over every leaf. Returns ``(value, sum_w)``."""
     out_v = np.empty(len(p))
     out_s = np.empty(len(p))
     for a in range(0, len(p), chunk):
-        w = weights(p[a:a + chunk], leaves["x"], leaves["y"], leaves["c"], leaves["sigma"], cutoff)
+        w = weights(p[a:a + chunk], leaves["x"], leaves["y"], leaves["c"], leaves["sigma"], cutoff, basis)
         s0 = w.sum(axis=1)
         out_v[a:a + chunk] = (w @ np.asarray(leaves["v"], np.float64)) / s0
         out_s[a:a + chunk] = s0
@@ -99,9 +132,12 @@ def rbf_bruteforce(p: np.ndarray, leaves: dict, cutoff: float, chunk: int = 2048
 class RBFField:
     """Eq. 2 by range queries: one k-d tree per cell size, radius = cutoff * max(sigma) * c."""
 
-    def __init__(self, leaves: dict, cutoff: float):
+    def __init__(self, leaves: dict, cutoff: float, basis: str = "gaussian"):
+        if basis not in BASES:
+            raise ValueError(f"unknown basis {basis!r}")
         self.L = {k: np.asarray(leaves[k], np.float64) for k in ("x", "y", "c", "v", "sigma")}
         self.cutoff = cutoff
+        self.basis = basis
         self.groups = []
         for c in np.unique(self.L["c"]):
             idx = np.nonzero(self.L["c"] == c)[0]
@@ -129,7 +165,7 @@ class RBFField:
         L = self.L
         r = np.hypot(L["x"][lj] - p[pi, 0], L["y"][lj] - p[pi, 1])
         q = r / (L["sigma"][lj] * L["c"][lj])
-        w = np.exp(-0.5 * q * q) - math.exp(-0.5 * self.cutoff * self.cutoff)
+        w = basis_weight(q, self.cutoff, self.basis)
         keep = w > 0.0
         pi, lj, w = pi[keep], lj[keep], w[keep]
         s0 = np.bincount(pi, weights=w, minlength=len(p))
@@ -139,7 +175,7 @@ class RBFField:
         return (val, s0, (pi, lj, w)) if return_terms else (val, s0)
 
 
-def discretize(cas, leaves: dict, dom, cutoff: float, field: RBFField = None) -> np.ndarray:
+def discretize(cas, leaves: dict, dom, cutoff: float, field: RBFField = None, basis: str = "gaussian") -> np.ndarray:
     """FP64 cascade texture ``[N][N]``: Eq. 2 at visible texels, ``-inf`` elsewhere."""
     N = cas.n
     vis = visibility(cas)
@@ -149,6 +185,6 @@ def discretize(cas, leaves: dict, dom, cutoff: float, field: RBFField = None) ->
         return tex
     p = clamp_to_domain(texel_centres(cas, ii, jj), dom)
     if field is None:
-        field = RBFField(leaves, cutoff)
+        field = RBFField(leaves, cutoff, basis)
     tex[jj, ii] = field.evaluate(p)[0]
     return tex

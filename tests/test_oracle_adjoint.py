@@ -15,8 +15,8 @@ def _small_scene(width=48, height=48, N=64):
     return s, cam, cs
 
 
-def _render(leaves, s, cam, cs):
-    field = discretize.RBFField(leaves, s.work.cutoff)
+def _render(leaves, s, cam, cs, basis="gaussian"):
+    field = discretize.RBFField(leaves, s.work.cutoff, basis)
     tex = np.stack([discretize.discretize(c, leaves, s.dom, s.work.cutoff, field) for c in cs])
     return raycast.raycast(cam, s.dom, cs, tex), field, tex
 
@@ -49,13 +49,14 @@ def test_texel_gradients_fd():
     assert checked >= 30
 
 
-def test_leaf_gradients_fd():
+@pytest.mark.parametrize("basis", discretize.BASES)
+def test_leaf_gradients_fd(basis):
     s, cam, cs = _small_scene()
     L = {k: np.asarray(v).copy() for k, v in s.leaves.items()}
     rng = np.random.default_rng(1003)
     Lt = dict(L, v=(L["v"] + rng.normal(0, 2.0, len(L["v"]))).astype(np.float32))
-    target = _render(Lt, s, cam, cs)[0]["depth"]
-    r0, field, _ = _render(L, s, cam, cs)
+    target = _render(Lt, s, cam, cs, basis)[0]["depth"]
+    r0, field, _ = _render(L, s, cam, cs, basis)
     loss0, gd = adjoint.l2_loss(r0["depth"], target)
     gtex = adjoint.texel_gradients(r0, gd, len(cs), cs[0].n)
     gv, gs = adjoint.leaf_gradients(cs, field, s.dom, gtex)
@@ -69,7 +70,7 @@ def test_leaf_gradients_fd():
             Lm = {k: v.astype(np.float64) for k, v in L.items()}
             Lp[name][j] += eps
             Lm[name][j] -= eps
-            rp, rm = _render(Lp, s, cam, cs)[0], _render(Lm, s, cam, cs)[0]
+            rp, rm = _render(Lp, s, cam, cs, basis)[0], _render(Lm, s, cam, cs, basis)[0]
             if not (np.array_equal(_hit_ids(rp), _hit_ids(r0)) and np.array_equal(_hit_ids(rm), _hit_ids(r0))):
                 continue
             fd = (adjoint.l2_loss(rp["depth"], target)[0] - adjoint.l2_loss(rm["depth"], target)[0]) / (2 * eps)
