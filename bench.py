@@ -427,6 +427,11 @@ def main():
                                                          R.ray_work(cam, backward=True)),
         "discretize_backward": lambda: api.discretize_backward(R.L, R.dom, cas, R.tex, gtex, gv, gs),
     }
+    # the same frame's textures with the other basis (Wendland C2 on the same support)
+    Lw = R.L.with_basis("wendland")
+    api.pack_leaves(Lw)
+    tex_w = torch.empty_like(R.tex)
+    stage["discretize_wendland"] = lambda: api.discretize(Lw, R.dom, cas, tex_w)
     if R.extra:
         X = R.extra[0]
         d_ter, h_ter = api.raycast(cam, R.dom, cas, R.tex, R.mip, None, None, None, R.ray_work(cam))
@@ -442,6 +447,7 @@ def main():
             "raycast_nearer_water": nearer,
         })
     stage_ms = {k: timed(f, args.steps, stream) for k, f in stage.items()}
+    del Lw, tex_w
     api.discretize(R.L, R.dom, cas, R.tex, R.mask)
     torch.cuda.synchronize()
     t_host = time.perf_counter()

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 7
+#define HFR_ABI_VERSION 8
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -100,6 +100,7 @@ typedef struct {
  *                                 (packed[p] is leaf order[p]), written by
  *                                 hfr_pack_leaves; s = sqrt(log2(e) / 2) / (sigma c),
  *                                 so that Eq. 1's Gaussian is exp2(-(s r)^2)
+ *                                 (HFR_BASIS_WENDLAND: s = 1 / (cutoff sigma c))
  *  level_radius      : float[max_depth + 1], written by hfr_pack_leaves: the
  *                      largest truncation radius cutoff * sigma_j * c_j of the
  *                      leaves of each level (0 where a level has none)
@@ -107,7 +108,15 @@ typedef struct {
  *                      arrays copied to the device); packed is stored in the
  *                      order it defines
  *  cutoff            : truncation radius in units of sigma (the paper's 3.5)
+ *  basis             : the weight function in Eq. 2 (HFR_BASIS_*); the packed
+ *                      records hold the scale of the basis they were packed for
  */
+#define HFR_BASIS_GAUSSIAN 0 /* Eq. 1: truncated Gaussian minus its value at the cutoff */
+/* Wendland's compactly supported C2 function (1 - u)^4 (4u + 1), u = r / (cutoff
+ * sigma c), 0 for u >= 1: the same support as the truncated Gaussian, so the same
+ * leaves influence the same texels.  The two-step design of Section 1 admits any
+ * reconstruction in the discretization; this one needs no truncation constant. */
+#define HFR_BASIS_WENDLAND 1
 typedef struct {
     int64_t n;
     const float* x;
@@ -122,6 +131,7 @@ typedef struct {
     int32_t max_depth;
     float cutoff;
     double x0, y0, side;
+    int32_t basis;
 } hfr_leaves;
 
 /* ------------------------------------------------------------------ misc */
@@ -239,8 +249,8 @@ hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_
 
 /* Writes L->packed (each record placed at its leaf's sorted position, found
  * through L->rank) and L->level_radius from x, y, v, c, sigma and cutoff
- * (call again whenever v or sigma change).  EINVAL on NULL pointers, n < 1,
- * cutoff <= 0, max_depth outside [0, 15]. */
+ * (call again whenever v, sigma or basis change).  EINVAL on NULL pointers,
+ * n < 1, cutoff <= 0, max_depth outside [0, 15], an unknown basis. */
 hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
 
 /* Discretization (Section 4, Eq. 1 and Eq. 2, and the visibility texture of
@@ -249,7 +259,8 @@ hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
  * polygon; a visible texel holds
  *   v_s = sum_j w_j v_j / sum_j w_j,
  *   w_j = max(0, exp(-(|p_j - p_s| / (sigma_j c_j))^2 / 2) - exp(-cutoff^2 / 2)),
- * evaluated at the texel centre clamped into the domain, summed over every
+ * (HFR_BASIS_WENDLAND: w_j = (1 - u)^4 (4u + 1) for u = |p_j - p_s| /
+ * (cutoff sigma_j c_j) < 1, else 0), evaluated at the texel centre clamped into the domain, summed over every
  * leaf with w_j > 0 (found per block of texels from L->rank and
  * L->level_radius); an invisible texel holds -inf.  tex: device float[K][N][N].  mask: device uint32
  * [K][N][(N + 31) / 32] visibility bits (bit i % 32 of word i / 32), or NULL.
@@ -338,6 +349,7 @@ hfr_status hfr_raycast_backward_surface(const hfr_camera* cam, const hfr_domain*
  *   grad_v[j]     += g_s w_j / S0
  *   grad_sigma[j] += g_s (v_j - v_s) / S0 * exp(-q^2/2) q^2 / sigma_j,
  *   q = |p_j - p_s| / (sigma_j c_j),
+ * (HFR_BASIS_WENDLAND: the last factor is 20 u^2 (1 - u)^3 / sigma_j for u < 1)
  * for every visible texel s with g_s = grad_tex[s] != 0, where S0 = sum_j w_j
  * and v_s = tex[s] (the forward output).  Visibility and the cascade fit
  * are treated as constants. */
@@ -423,8 +435,9 @@ typedef struct {
  * and returns a plan (*out).  Cameras must be set (hfr_batch_set_cameras)
  * before the first launch.  EINVAL: n_fields or n_views outside [1, 4096],
  * a view naming a missing field, K, N or image size out of range, NULL
- * buffers, or a total work count above 2^31.  ENOMEM / EDEVICE: allocation
- * failures.  Synchronous. */
+ * buffers, or a total work count above 2^31.  EUNSUPPORTED: a field whose
+ * basis is not HFR_BASIS_GAUSSIAN.  ENOMEM / EDEVICE: allocation failures.
+ * Synchronous. */
 hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32_t n_fields, const hfr_batch_view* views,
                                  int32_t n_views, hfr_batch_plan** out);
 void hfr_batch_plan_destroy(hfr_batch_plan* plan);

@@ -204,8 +204,14 @@ def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: fl
 
 # ---------------------------------------------------------- per frame (device)
 
+BASIS_GAUSSIAN = 0  # Eq. 1
+BASIS_WENDLAND = 1  # Wendland's C2 function on the same support
+BASES = {"gaussian": BASIS_GAUSSIAN, "wendland": BASIS_WENDLAND}
+
+
 class DeviceLeaves:
-    """Leaf arrays, level index and per-level radii resident on the GPU (torch tensors)."""
+    """Leaf arrays, level index and per-level radii resident on the GPU (torch tensors).  ``basis``
+    (``BASIS_*``) is the weight function the packed records are written for."""
 
     def __init__(self, leaves: dict, index, side: float, max_depth: int, cutoff: float,
                  x0: float = 0.0, y0: float = 0.0, device: str = "cuda"):
@@ -223,6 +229,7 @@ class DeviceLeaves:
         self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=device)
         self.max_depth, self.cutoff = int(max_depth), float(cutoff)
         self.x0, self.y0, self.side = float(x0), float(y0), float(side)
+        self.basis = BASIS_GAUSSIAN
 
     @classmethod
     def from_device(cls, leaves: dict, sigma, side: float, max_depth: int, cutoff: float, x0: float = 0.0,
@@ -243,6 +250,7 @@ class DeviceLeaves:
         self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=dev)
         self.max_depth, self.cutoff = int(max_depth), float(cutoff)
         self.x0, self.y0, self.side = float(x0), float(y0), float(side)
+        self.basis = BASIS_GAUSSIAN
         return self
 
     def with_values(self, v) -> "DeviceLeaves":
@@ -258,6 +266,20 @@ class DeviceLeaves:
         other.level_radius = torch.zeros_like(self.level_radius)
         return other
 
+    def with_basis(self, basis) -> "DeviceLeaves":
+        """The same heightfield reconstructed with another weight function (``BASIS_*`` or its name):
+        shares every leaf array and the level index; its own packed records (call ``pack_leaves``)."""
+        import torch
+        b = BASES[basis] if isinstance(basis, str) else int(basis)
+        if b not in BASES.values():
+            raise ValueError(f"unknown basis {basis!r}")
+        other = object.__new__(DeviceLeaves)
+        other.__dict__.update(self.__dict__)
+        other.basis = b
+        other.packed = torch.empty_like(self.packed)
+        other.level_radius = torch.zeros_like(self.level_radius)
+        return other
+
     def struct(self) -> Leaves:
         import torch
         for name in ("x", "y", "c", "v", "sigma", "packed", "level_radius"):
@@ -267,7 +289,7 @@ class DeviceLeaves:
         return Leaves(self.n, self.x.data_ptr(), self.y.data_ptr(), self.c.data_ptr(), self.v.data_ptr(),
                       self.sigma.data_ptr(), self.packed.data_ptr(), self.level_radius.data_ptr(),
                       self.rank.data_ptr(), self.order.data_ptr(), self.max_depth, self.cutoff, self.x0, self.y0,
-                      self.side)
+                      self.side, self.basis)
 
 
 def pack_leaves(L: DeviceLeaves, stream=None) -> None:

@@ -157,6 +157,8 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     std::vector<bool> field_bwd(n_fields);
     for (int f = 0; f < n_fields; ++f) {
         const hfr_batch_field& F = fields[f];
+        if (F.leaves.basis != HFR_BASIS_GAUSSIAN)
+            return hfr_fail(HFR_EUNSUPPORTED, "field %d: batched launches use the Gaussian basis only", f);
         hfr_status st = leaf_tables(&F.leaves, false, &tables[f]);
         if (st == HFR_OK) st = check_domain(&F.dom);
         if (st != HFR_OK) return hfr_fail(st, "field %d: %s", f, hfr_last_error());

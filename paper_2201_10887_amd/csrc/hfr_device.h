@@ -133,8 +133,8 @@ struct Tables {
     const float* sigma;
     int n, max_depth;
     double x0, y0, side, inv_side;
-    float E;   // exp(-cutoff^2 / 2)
-    float T2;  // (s r)^2 at the truncation radius: cutoff^2 log2(e) / 2
+    float E;   // exp(-cutoff^2 / 2) (Gaussian basis; 0 otherwise)
+    float T2;  // (s r)^2 at the truncation radius: cutoff^2 log2(e) / 2 (Wendland basis: 1)
 };
 
 // Per-cascade ray-cast constants.

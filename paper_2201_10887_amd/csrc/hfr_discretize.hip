@@ -18,7 +18,8 @@
 //     truncation radius reaches the block rectangle goes to LDS as
 //     (s x, s y, s, v), positions relative to the block origin (FP64
 //     difference, then FP32), with s = sqrt(log2(e) / 2) / (sigma c) so that
-//     Eq. 1's Gaussian is exp2(-(s r)^2).
+//     Eq. 1's Gaussian is exp2(-(s r)^2) (Wendland basis: s = 1 / (k sigma c),
+//     so that (s r)^2 is the squared distance in units of the support).
 //  4. Each wave keeps the records whose own truncation radius reaches its
 //     tile (a compact copy in LDS), and every lane (texel) runs Eq. 1 / Eq. 2
 //     over them with broadcast LDS reads and immediate offsets, subtracting
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restric
                                                           const float* __restrict__ v, const float* __restrict__ c,
                                                           const float* __restrict__ sigma,
                                                           const int32_t* __restrict__ rank, double x0, double y0,
-                                                          float cutoff, float side, int max_depth,
+                                                          float cutoff, float scale, float side, int max_depth,
                                                           float4* __restrict__ out, float* __restrict__ radius,
                                                           int64_t n)
 {
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restric
         const int i = min(max((int)floor(((double)xa - x0) / ca), 0), S - 1);
         const int j = min(max((int)floor(((double)ya - y0) / ca), 0), S - 1);
         const int64_t p = rank[((int64_t(1) << (2 * l)) - 1) / 3 + l + (int64_t)j * S + i];
-        if (p >= 0 && p < n) out[p] = make_float4(xa, ya, v[a], sqrtf(HALF_LOG2E) / sc);
+        if (p >= 0 && p < n) out[p] = make_float4(xa, ya, v[a], scale / sc);
         const float R = cutoff * sc * 1.00001f;
         atomicMax(&level_max[l], __float_as_int(R));
     }
@@ -334,6 +335,39 @@ __device__ __forceinline__ float rbf_weight(float dx, float dy, float E)
     return __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-fmaf(dx, dx, dy * dy)) - E, 0.0f, 1.0f);
 }
 
+// Wendland's C2 function (1 - u)^4 (4u + 1) of u = (s r), 0 from u = 1 on.
+__device__ __forceinline__ float wendland_weight(float dx, float dy)
+{
+    const float u = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+    const float t = __builtin_amdgcn_fmed3f(1.0f - u, 0.0f, 1.0f);
+    const float t2 = t * t;
+    return t2 * t2 * fmaf(4.0f, u, 1.0f);
+}
+
+template <int BASIS>
+__device__ __forceinline__ float pair_weight(float dx, float dy, float E)
+{
+    if constexpr (BASIS == HFR_BASIS_WENDLAND) return wendland_weight(dx, dy);
+    else return rbf_weight(dx, dy, E);
+}
+
+// Weight w and sigma dw/dsigma of one pair from r2 = (s r)^2.
+template <int BASIS>
+__device__ __forceinline__ void pair_weight_dsigma(float r2, float E, float* w, float* sdw)
+{
+    if constexpr (BASIS == HFR_BASIS_WENDLAND) {
+        const float u = __builtin_amdgcn_sqrtf(r2);
+        const float t = fmaxf(1.0f - u, 0.0f);
+        const float t3 = t * t * t;
+        *w = t3 * t * fmaf(4.0f, u, 1.0f);
+        *sdw = 20.0f * r2 * t3;  // (1 - u)^4 (4u + 1) has d/du = -20 u (1 - u)^3, and u scales as 1 / sigma
+    } else {
+        const float ex = __builtin_amdgcn_exp2f(-r2);
+        *w = ex - E;
+        *sdw = ex * r2 * (2.0f / LOG2E);  // r2 = q^2 log2(e) / 2
+    }
+}
+
 struct TileFrame {
     float x0, x1, y0, y1;  // tile rectangle relative to the block origin
     float npx, npy;        // minus the lane's texel centre relative to the block origin
@@ -364,6 +398,7 @@ struct DiscShared {
 
 // Texels of block (bx, by) of one cascade; every thread of the workgroup
 // takes part.
+template <int BASIS>
 __device__ __forceinline__ void discretize_block(const Tables& T, const TexCascade& C, const Dom2& D, int bx, int by,
                                                  float* __restrict__ tex, uint16_t* __restrict__ mask, DiscShared& sh)
 {
@@ -408,7 +443,7 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
                     wave_sync();
                     for (int a = 0; a < nt; ++a) {
                         const float4 r = trec[a];
-                        const float g = rbf_weight(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
+                        const float g = pair_weight<BASIS>(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
                         s0 += g;
                         s1 = fmaf(g, r.w, s1);
                     }
@@ -424,14 +459,14 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float4 r = trec[a + u];
-                    const float g = rbf_weight(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
+                    const float g = pair_weight<BASIS>(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
                     s0 += g;
                     s1 = fmaf(g, r.w, s1);
                 }
             }
             for (; a < nt; ++a) {
                 const float4 r = trec[a];
-                const float g = rbf_weight(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
+                const float g = pair_weight<BASIS>(fmaf(f.npx, r.z, r.x), fmaf(f.npy, r.z, r.y), E);
                 s0 += g;
                 s1 = fmaf(g, r.w, s1);
             }
@@ -467,6 +502,7 @@ __device__ inline int fused_block(const CascadeSet& S, int gx, int gy, int* bx, 
 
 // 8 waves per SIMD (at most 64 VGPRs, no spills; 8 blocks of LDS fit a CU): the near
 // cascades wait on rank-table and record loads, and more resident waves hide that.
+template <int BASIS>
 __global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, CascadeSet S, Dom2 D, int gx, int gy,
                                                          float* __restrict__ tex, uint16_t* __restrict__ mask)
 {
@@ -475,7 +511,8 @@ __global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, CascadeSet
     const int k = __builtin_amdgcn_readfirstlane(fused_block(S, gx, gy, &bx, &by));
     const TexCascade& C = S.c[k];
     const int64_t N = C.n;
-    discretize_block(T, C, D, bx, by, tex + k * N * N, mask ? mask + k * N * 2 * ((N + 31) / 32) : nullptr, sh);
+    discretize_block<BASIS>(T, C, D, bx, by, tex + k * N * N, mask ? mask + k * N * 2 * ((N + 31) / 32) : nullptr,
+                            sh);
 }
 
 // Adjoint of Eq. 2 / Eq. 1.  Lanes first own texels (S0 of each texel), then
@@ -492,6 +529,7 @@ struct DiscBwdShared {
     int any_act;
 };
 
+template <int BASIS>
 __device__ __forceinline__ void discretize_backward_block(const Tables& T, const TexCascade& C, const Dom2& D, int bx,
                                                           int by, const float* __restrict__ tex,
                                                           const float* __restrict__ gtex, float* __restrict__ gv,
@@ -543,7 +581,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
                         const int t = __ffsll((unsigned long long)m) - 1;
                         m &= m - 1;
                         const float4 q = brec[c0 + t];
-                        s0 += rbf_weight(fmaf(f.npx, q.z, q.x), fmaf(f.npy, q.z, q.y), E);
+                        s0 += pair_weight<BASIS>(fmaf(f.npx, q.z, q.x), fmaf(f.npy, q.z, q.y), E);
                     }
                 }
             }
@@ -582,12 +620,12 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
                         const float tnx = __shfl(f.npx, t), tny = __shfl(f.npy, t), tg = __shfl(gn, t),
                                     tv = __shfl(vs, t);
                         const float dx = fmaf(tnx, q.z, q.x), dy = fmaf(tny, q.z, q.y);
-                        const float r2 = fmaf(dx, dx, dy * dy);  // (s r)^2 = q^2 log2(e) / 2
-                        const float ex = __builtin_amdgcn_exp2f(-r2);
-                        const float w = ex - E;
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        float w, sdw;
+                        pair_weight_dsigma<BASIS>(r2, E, &w, &sdw);
                         if (w > 0.0f) {
                             acc_v = fmaf(tg, w, acc_v);
-                            acc_s = fmaf(tg * (q.w - tv), ex * r2 * (2.0f / LOG2E) / sj, acc_s);
+                            acc_s = fmaf(tg * (q.w - tv), sdw / sj, acc_s);
                         }
                     }
                     if (own && (acc_v != 0.0f || acc_s != 0.0f)) {
@@ -602,6 +640,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     }
 }
 
+template <int BASIS>
 __global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, CascadeSet S, Dom2 D, int gx, int gy,
                                                                   const float* __restrict__ tex,
                                                                   const float* __restrict__ gtex,
@@ -612,7 +651,7 @@ __global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, C
     const int k = __builtin_amdgcn_readfirstlane(fused_block(S, gx, gy, &bx, &by));
     const TexCascade& C = S.c[k];
     const int64_t N = C.n;
-    discretize_backward_block(T, C, D, bx, by, tex + k * N * N, gtex + k * N * N, gv, gs, sh);
+    discretize_backward_block<BASIS>(T, C, D, bx, by, tex + k * N * N, gtex + k * N * N, gv, gs, sh);
 }
 
 // Persistent form over every cascade of every view of a batch: each
@@ -655,8 +694,9 @@ __global__ __launch_bounds__(256, 7) void discretize_batch_kernel(BatchDev P)
             const BatchField& F = as_constant(P.fields, it.field);
             const int local = w - item_lo;
             const int bx = local % it.gx, by = local / it.gx;
-            if constexpr (BACKWARD) discretize_backward_block(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs, sh);
-            else discretize_block(F.T, it.C, F.D, bx, by, it.tex, it.mask, sh);
+            if constexpr (BACKWARD)
+                discretize_backward_block<HFR_BASIS_GAUSSIAN>(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs, sh);
+            else discretize_block<HFR_BASIS_GAUSSIAN>(F.T, it.C, F.D, bx, by, it.tex, it.mask, sh);
             __syncthreads();  // LDS is reused by the next block of the run
         }
     }
@@ -675,9 +715,12 @@ hfr_status leaf_tables(const hfr_leaves* L, bool backward, Tables* out)
     HFR_REQUIRE(std::isfinite(L->cutoff) && L->cutoff > 0, "cutoff must be positive");
     HFR_REQUIRE(std::isfinite(L->side) && L->side > 0 && std::isfinite(L->x0) && std::isfinite(L->y0),
                 "invalid lattice square");
+    HFR_REQUIRE(L->basis == HFR_BASIS_GAUSSIAN || L->basis == HFR_BASIS_WENDLAND, "unknown basis %d", L->basis);
+    const bool gauss = L->basis == HFR_BASIS_GAUSSIAN;
     *out = Tables{reinterpret_cast<const float4*>(L->packed), L->level_radius, L->rank, L->order, L->sigma, (int)L->n,
-                  L->max_depth, L->x0, L->y0, L->side, 1.0 / L->side, std::exp(-0.5f * L->cutoff * L->cutoff),
-                  0.5f * LOG2E * L->cutoff * L->cutoff};
+                  L->max_depth, L->x0, L->y0, L->side, 1.0 / L->side,
+                  gauss ? std::exp(-0.5f * L->cutoff * L->cutoff) : 0.0f,
+                  gauss ? 0.5f * LOG2E * L->cutoff * L->cutoff : 1.0f};
     return HFR_OK;
 }
 
@@ -691,12 +734,15 @@ extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
     HFR_REQUIRE(L->max_depth >= 0 && L->max_depth <= 15, "max_depth %d outside [0, 15]", L->max_depth);
     HFR_REQUIRE(std::isfinite(L->cutoff) && L->cutoff > 0, "cutoff must be positive");
     HFR_REQUIRE(std::isfinite(L->side) && L->side > 0, "side must be positive");
+    HFR_REQUIRE(L->basis == HFR_BASIS_GAUSSIAN || L->basis == HFR_BASIS_WENDLAND, "unknown basis %d", L->basis);
+    // record scale: exp2(-(s r)^2) is Eq. 1's Gaussian; for Wendland s r is r over the support radius
+    const float scale = L->basis == HFR_BASIS_GAUSSIAN ? std::sqrt(HALF_LOG2E) : 1.0f / L->cutoff;
     hipStream_t s = (hipStream_t)stream;
     zero_floats_kernel<<<1, 64, 0, s>>>(L->level_radius, L->max_depth + 1);
     HFR_LAUNCH_CHECK("pack_leaves (radius reset)");
     const int64_t blocks = std::min<int64_t>((L->n + 255) / 256, 2048);
     pack_leaves_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
-        L->x, L->y, L->v, L->c, L->sigma, L->rank, L->x0, L->y0, L->cutoff, (float)L->side, L->max_depth,
+        L->x, L->y, L->v, L->c, L->sigma, L->rank, L->x0, L->y0, L->cutoff, scale, (float)L->side, L->max_depth,
         reinterpret_cast<float4*>(L->packed), L->level_radius, L->n);
     HFR_LAUNCH_CHECK("pack_leaves");
     return hfr_ok();
@@ -719,9 +765,13 @@ extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom,
         CascadeSet S;
         S.K = std::min(FUSE, K - k0);
         for (int k = 0; k < S.K; ++k) S.c[k] = tex_cascade(cas[k0 + k]);
-        discretize_kernel<<<dim3(gx * gy * S.K), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
-            T, S, D, gx, gy, tex + (int64_t)k0 * N * N,
-            mask ? reinterpret_cast<uint16_t*>(mask + (int64_t)k0 * N * words) : nullptr);
+        float* t = tex + (int64_t)k0 * N * N;
+        uint16_t* m = mask ? reinterpret_cast<uint16_t*>(mask + (int64_t)k0 * N * words) : nullptr;
+        const dim3 grid(gx * gy * S.K), block(64 * WAVES);
+        if (L->basis == HFR_BASIS_WENDLAND)
+            discretize_kernel<HFR_BASIS_WENDLAND><<<grid, block, 0, (hipStream_t)stream>>>(T, S, D, gx, gy, t, m);
+        else
+            discretize_kernel<HFR_BASIS_GAUSSIAN><<<grid, block, 0, (hipStream_t)stream>>>(T, S, D, gx, gy, t, m);
         HFR_LAUNCH_CHECK("discretize");
     }
     return hfr_ok();
@@ -744,8 +794,15 @@ extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_dom
         CascadeSet S;
         S.K = std::min(FUSE, K - k0);
         for (int k = 0; k < S.K; ++k) S.c[k] = tex_cascade(cas[k0 + k]);
-        discretize_backward_kernel<<<dim3(gx * gy * S.K), dim3(64 * WAVES), 0, (hipStream_t)stream>>>(
-            T, S, D, gx, gy, tex + (int64_t)k0 * N * N, grad_tex + (int64_t)k0 * N * N, grad_v, grad_sigma);
+        const float* t = tex + (int64_t)k0 * N * N;
+        const float* g = grad_tex + (int64_t)k0 * N * N;
+        const dim3 grid(gx * gy * S.K), block(64 * WAVES);
+        if (L->basis == HFR_BASIS_WENDLAND)
+            discretize_backward_kernel<HFR_BASIS_WENDLAND><<<grid, block, 0, (hipStream_t)stream>>>(
+                T, S, D, gx, gy, t, g, grad_v, grad_sigma);
+        else
+            discretize_backward_kernel<HFR_BASIS_GAUSSIAN><<<grid, block, 0, (hipStream_t)stream>>>(
+                T, S, D, gx, gy, t, g, grad_v, grad_sigma);
         HFR_LAUNCH_CHECK("discretize_backward");
     }
     return hfr_ok();

@@ -19,15 +19,18 @@ from . import api
 class Renderer:
     def __init__(self, leaves: dict, side: float, max_depth: int, cutoff: float, cascades: int, tex_n: int,
                  split_lambda: float, overlap: float, device: str = "cuda",
-                 x0: float = 0.0, y0: float = 0.0):
+                 x0: float = 0.0, y0: float = 0.0, basis="gaussian"):
         index = api.build_level_index(leaves, side, max_depth, x0, y0)
         L = api.DeviceLeaves(leaves, index, side, max_depth, cutoff, x0, y0, device=device)
+        if basis != "gaussian":
+            L = L.with_basis(basis)
         self._setup(L, float(np.min(leaves["c"])), float(np.min(leaves["v"])), float(np.max(leaves["v"])),
                     cascades, tex_n, split_lambda, overlap, device)
 
     @classmethod
     def from_raster(cls, dem, side: float, max_depth: int, tau: float, sigma, cutoff: float, cascades: int,
-                    tex_n: int, split_lambda: float, overlap: float, x0: float = 0.0, y0: float = 0.0) -> "Renderer":
+                    tex_n: int, split_lambda: float, overlap: float, x0: float = 0.0, y0: float = 0.0,
+                    basis="gaussian") -> "Renderer":
         """The whole start-up on the device from a device raster (float32 [n][n] tensor): the quadtree
         and its level index (build_quadtree_device) and the packed records.  Only the leaf count, the
         smallest cell and the value range come back to the host.  ``sigma``: widths per leaf (tensor,
@@ -35,6 +38,8 @@ class Renderer:
         import torch
         q = api.build_quadtree_device(dem, side, max_depth, tau, x0, y0)
         L = api.DeviceLeaves.from_device(q, sigma, side, max_depth, cutoff, x0, y0)
+        if basis != "gaussian":
+            L = L.with_basis(basis)
         c_min, v_min, v_max = torch.stack([L.c.min(), L.v.min(), L.v.max()]).tolist()
         self = object.__new__(cls)
         self._setup(L, c_min, v_min, v_max, cascades, tex_n, split_lambda, overlap, str(dem.device))

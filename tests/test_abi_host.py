@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 7
+    assert api.abi_version() == 8
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -215,6 +215,12 @@ def test_invalid_arguments_rejected_before_launch():
     _raise_einval("hfr_discretize_backward", ctypes.byref(L3), ctypes.byref(dom), cs, 2, dummy, dummy, dummy,
                   dummy, None)
     _raise_einval("hfr_pack_leaves", ctypes.byref(api.Leaves()), None)
+    # unknown basis
+    L4 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 3.5, 0.0, 0.0, 1.0, 2)
+    _raise_einval("hfr_pack_leaves", ctypes.byref(L4), None)
+    _raise_einval("hfr_discretize", ctypes.byref(L4), ctypes.byref(dom), cs, 2, dummy, None, None)
+    _raise_einval("hfr_discretize_backward", ctypes.byref(L4), ctypes.byref(dom), cs, 2, dummy, dummy, dummy,
+                  dummy, None)
     # fit: vertical view, N not a power of two, K out of range
     vert = api.camera(synth.Camera((50, 50, 50), 0.0, -math.pi / 2, 1.0, 64, 64))
     out = (api.Cascade * 8)()
@@ -226,7 +232,7 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 7
+    assert lib.hfr_abi_version() == 8
 
 
 def test_batch_arguments_rejected_before_any_device_call():
@@ -258,6 +264,10 @@ def test_batch_arguments_rejected_before_any_device_call():
     bad[0].leaves, bad[0].dom = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, None, 4,
                                            3.5, 0.0, 0.0, 100.0), dom
     _raise_einval("hfr_batch_plan_create", bad, 1, view(), 1, ctypes.byref(h))
+    wend = (_lib.BatchField * 1)()
+    wend[0].leaves, wend[0].dom = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4,
+                                             3.5, 0.0, 0.0, 100.0, api.BASIS_WENDLAND), dom
+    assert lib.hfr_batch_plan_create(wend, 1, view(), 1, ctypes.byref(h)) == -5  # EUNSUPPORTED
     assert h.value is None
     t = _lib.BatchTuning(4, 4, 12, 4)
     _raise_einval("hfr_batch_set_tuning", None, ctypes.byref(t))

@@ -70,6 +70,26 @@ def test_packed_records_follow_the_level_order(gpu, medium):
         assert abs(radius[level] - want * 1.00001) <= 1e-5 * max(want, 1.0), level
 
 
+def test_wendland_discretize_sampled(gpu, medium):
+    """The Wendland basis at the bench's launch shape: sampled texels of all four cascades."""
+    m = medium
+    W = m["L"].with_basis("wendland")
+    api.pack_leaves(W)
+    tex = api.discretize(W, m["dom"], m["cas"]).cpu().numpy()
+    field = odisc.RBFField(m["leaves"], m["w"].cutoff, "wendland")
+    rng = np.random.default_rng(2025)
+    for k, cas in enumerate(m["cs"]):
+        vis = odisc.visibility(cas)
+        assert np.array_equal(vis, np.isfinite(tex[k]))
+        jj, ii = np.nonzero(vis)
+        pick = rng.choice(len(jj), 2000, replace=False)
+        p = odisc.clamp_to_domain(odisc.texel_centres(cas, ii[pick], jj[pick]), m["dom"])
+        ref, _ = field.evaluate(p)
+        err = np.abs(tex[k][jj[pick], ii[pick]] - ref)
+        assert np.all(err <= G.texel_tolerance(m["leaves"], ref)), (k, err.max())
+    del W
+
+
 def test_discretize_full_frame_sampled(gpu, medium):
     m = medium
     K, N = len(m["cas"]), m["cas"][0].n
