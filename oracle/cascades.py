@@ -31,6 +31,14 @@ Steps, in the paper's order:
    ``(x0 + i hx, y0 + j hy)`` with ``hx = ext_x / (N - 1)`` (reading: the
    texels may be anisotropic; the paper asks for the largest used area).
 
+A second fit keeps texel lattices fixed in the world between frames (for
+reusing texels, not in the paper): each axis takes the smallest texel
+spacing ``h = c_min 2^(e/4)`` (an integer ``e``, quarter octaves of the
+smallest cell) for which the lattice origin, the largest multiple of ``h``
+from the domain origin at or below the box, puts the last texel centre at
+or beyond the box.  Two frames that pick the same ``h`` share the lattice
+(their origins differ by whole texels).
+
 Pinned by ``tests/test_oracle_cascades.py``: the three-cascade logarithmic
 splits in closed form, a flat box whose visible area is the closed-form
 trapezoid of the four corner rays, coverage of the hull by the cascades,
@@ -168,7 +176,25 @@ def snap_axis(lo: float, hi: float, origin: float, c_min: float, N: int) -> tupl
     return x0, ext / (N - 1)
 
 
-def fit_cascades(cam, dom, K: int, N: int, lam: float, omega: float, c_min: float) -> List[Cascade]:
+QUARTER_OCTAVES = (1.0, 2.0 ** 0.25, 2.0 ** 0.5, 2.0 ** 0.75)
+
+
+def snap_axis_aligned(lo: float, hi: float, origin: float, c_min: float, N: int) -> tuple:
+    """Fixed-lattice fit of one axis: spacing on the quarter-octave ladder of ``c_min``, origin a
+    multiple of the spacing; the smallest spacing that covers ``[lo, hi]``."""
+    need = max(hi - lo, 0.0) / (N - 1)
+    e = math.floor(4.0 * math.log2(need / c_min)) - 1 if need > 0 else -64
+    while True:
+        q, r = divmod(e, 4)
+        h = math.ldexp(c_min * QUARTER_OCTAVES[r], q)
+        x0 = origin + math.floor((lo - origin) / h + SNAP_TOL) * h
+        if x0 + (N - 1) * h >= hi - SNAP_TOL * h:
+            return x0, h
+        e += 1
+
+
+def fit_cascades(cam, dom, K: int, N: int, lam: float, omega: float, c_min: float,
+                 aligned: bool = False) -> List[Cascade]:
     if K < 1 or N < 2 or N & (N - 1):
         raise ValueError("need K >= 1 and N a power of two >= 2")
     fwd, _, _ = basis(cam)
@@ -204,7 +230,8 @@ def fit_cascades(cam, dom, K: int, N: int, lam: float, omega: float, c_min: floa
         if len(poly) == 0:
             out.append(dataclasses.replace(empty, near=near, far=far, split=split))
             continue
-        x0, hx = snap_axis(poly[:, 0].min(), poly[:, 0].max(), dom.x0, c_min, N)
-        y0, hy = snap_axis(poly[:, 1].min(), poly[:, 1].max(), dom.y0, c_min, N)
+        snap = snap_axis_aligned if aligned else snap_axis
+        x0, hx = snap(poly[:, 0].min(), poly[:, 0].max(), dom.x0, c_min, N)
+        y0, hy = snap(poly[:, 1].min(), poly[:, 1].max(), dom.y0, c_min, N)
         out.append(Cascade(near, far, split, origin.copy(), vhat.copy(), x0, y0, hx, hy, N, poly))
     return out

@@ -150,3 +150,32 @@ def test_fit_misses_box():
     dom = synth.Domain(0.0, 0.0, 100.0, 100.0, 0.0, 10.0)
     cs = cascades.fit_cascades(_cam((50, -500, 50), 180, -10), dom, 3, 64, 1.0, 0.05, 1.0)
     assert all(len(c.poly) == 0 for c in cs)
+
+
+@pytest.mark.parametrize("pos,yaw,pitch", CAMS)
+@pytest.mark.parametrize("N", [64, 256])
+def test_aligned_fit_lattice(pos, yaw, pitch, N):
+    """Fixed-lattice fit: same polygons as the stable fit; spacing on the quarter-octave ladder,
+    origin a whole number of texels from the domain origin, the box covered, and (brute force over
+    the ladder) no smaller spacing would cover it."""
+    dom = synth.Domain(0.0, 0.0, 1024.0, 1024.0, 5.0, 300.0)
+    cam = _cam(pos, yaw, pitch, 256, 256)
+    c_min = 16.0
+    st = cascades.fit_cascades(cam, dom, 3, N, 0.5, 0.05, c_min)
+    al = cascades.fit_cascades(cam, dom, 3, N, 0.5, 0.05, c_min, aligned=True)
+    for a, b in zip(st, al):
+        assert (a.near, a.far, a.split) == (b.near, b.far, b.split) and np.array_equal(a.poly, b.poly)
+        if not len(b.poly):
+            continue
+        for o, h, base, lo, hi in ((b.x0, b.hx, dom.x0, b.poly[:, 0].min(), b.poly[:, 0].max()),
+                                   (b.y0, b.hy, dom.y0, b.poly[:, 1].min(), b.poly[:, 1].max())):
+            e = 4.0 * math.log2(h / c_min)
+            assert abs(e - round(e)) < 1e-9
+            m = (o - base) / h
+            assert abs(m - round(m)) < 1e-9
+            assert o <= lo + 1e-9 * h and o + (N - 1) * h >= hi - 1e-9 * h
+            # the ladder step below fails with its own origin
+            hs = c_min * 2.0 ** ((round(e) - 1) / 4.0)
+            os_ = base + math.floor((lo - base) / hs + 1e-9) * hs
+            assert os_ + (N - 1) * hs < hi - 1e-9 * hs
+            assert h < 2.0 ** 0.25 * (hi - lo) / (N - 2) + 1e-9
