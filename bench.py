@@ -90,6 +90,51 @@ def startup_ms(R, dem, w) -> dict:
             "level_index_host": round(t_index, 1)}
 
 
+def texel_reuse_flight(R, cam, depth, hit, frames=32, step=2.0, yaw_step=0.05) -> dict:
+    """Forward frames along a flight (``step`` m per frame along the view, turning ``yaw_step`` deg per
+    frame): the stable fit with every texel computed, the fixed-lattice fit with every texel computed,
+    and the fixed-lattice fit copying the blocks the previous frame holds.  ms per frame over the
+    whole flight (host fits included), and the share of visible blocks copied."""
+    import torch
+    from paper_2201_10887_amd import api, synth
+    path = synth.camera_path(cam, frames, step, yaw_step)
+    aligned = [api.fit_cascades(c, R.dom, R.K, R.N, R.lam, R.overlap, R.c_min, aligned=True) for c in path]
+
+    def flight(fn):
+        fn(0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for f in range(frames):
+            fn(f)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / frames
+
+    R.set_texel_reuse(False)
+    ms_stable = flight(lambda f: R.forward(path[f], None, depth, hit))
+    ms_aligned = flight(lambda f: R.forward(path[f], aligned[f], depth, hit))
+    R.set_texel_reuse(True)
+    ms_reuse = flight(lambda f: R.forward(path[f], None, depth, hit))
+    # copied share: one more flight, counting visible 16 x 16 blocks per frame from the masks
+    R.set_texel_reuse(True)
+    R.count_reused = True
+    R.reused_blocks.zero_()
+    visible = 0
+    for f in range(frames):
+        R.forward(path[f], None, depth, hit)
+        if f > 0:
+            for _, _, mask, _ in R.surfaces():
+                m = mask.view(torch.int16).reshape(R.K, R.N // 16, 16, -1)
+                visible += int((m != 0).any(dim=2).sum())
+    copied = int(R.reused_blocks.item())
+    R.count_reused = False
+    R.set_texel_reuse(False)
+    return {"frames": frames, "step_m": step, "yaw_step_deg": yaw_step, "ms_per_frame_stable_fit": round(ms_stable, 4),
+            "ms_per_frame_fixed_lattice": round(ms_aligned, 4), "ms_per_frame_reuse": round(ms_reuse, 4),
+            "copied_block_fraction": round(copied / max(visible, 1), 4)}
+
+
 def timed(fn, steps, stream):
     import torch
     torch.cuda.synchronize()
@@ -457,6 +502,8 @@ def main():
 
     startup = startup_ms(R, dem, w)
     work = discretize_work(R, cas, leaves, w)
+    reuse = texel_reuse_flight(R, cam, depth, hit)
+    print(f"[bench] texel reuse along a flight: {reuse}", file=sys.stderr, flush=True)
     vis_texels, pairs = work["visible_texels"], work["pairs"]
     forward()  # leave the full frame (every surface) in depth / hit
     torch.cuda.synchronize()
@@ -505,6 +552,7 @@ def main():
         "long_ray_queue": {"forward": R.long_ray_queue, "adjoint": R.long_ray_queue_backward, "tuning_ms": tuned},
         "fit_cascades_host_us": round(fit_us, 1),
         "startup_ms": startup,
+        "texel_reuse_flight": reuse,
         "gtexel_per_s": round(vis_texels / (stage_ms["discretize"] * 1e-3) / 1e9, 3),
         "gtexel_per_s_all": round(K * R.N * R.N / (stage_ms["discretize"] * 1e-3) / 1e9, 3),
         "grays_per_s": round(W * H / (stage_ms["raycast"] * 1e-3) / 1e9, 3),

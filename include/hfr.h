@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 8
+#define HFR_ABI_VERSION 9
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -245,6 +245,19 @@ hfr_status hfr_build_level_index(int64_t n, const float* x, const float* y, cons
 hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N,
                             double lambda, double overlap, double c_min, hfr_cascade* out);
 
+/* The same cascades with texel lattices fixed in the world, so that texels
+ * can be reused between frames (hfr_discretize_reuse; not in the paper,
+ * whose stable fit of Section 3 keeps the box corners on the c_min lattice
+ * but lets the texel spacing follow the box).  Polygons, near, far and
+ * split are hfr_fit_cascades'; each axis's spacing h is the smallest
+ * c_min 2^(e/4), e an integer, for which the lattice origin (the largest
+ * whole multiple of h from the domain origin at or below the box) puts the
+ * last texel centre at or beyond the box.  The spacing exceeds the stable
+ * fit's by at most a factor 2^(1/4) (N - 1) / (N - 2).  Same arguments and
+ * errors as hfr_fit_cascades. */
+hfr_status hfr_fit_cascades_aligned(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N,
+                                    double lambda, double overlap, double c_min, hfr_cascade* out);
+
 /* ------------------------------------------------------- per frame (device) */
 
 /* Writes L->packed (each record placed at its leaf's sorted position, found
@@ -269,6 +282,24 @@ hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
  * [2, HFR_MAX_TEX_N], missing leaf arrays. */
 hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas,
                           int32_t K, float* tex, uint32_t* mask, hfr_stream stream);
+
+/* hfr_discretize for the next frame of a camera path, reusing the previous
+ * frame's texels (not in the paper; its approximation pass is the cost it
+ * names).  prev_cas: the previous frame's host cascades [K]; prev_tex: its
+ * device textures [K][N][N], which must not overlap tex.  Where a cascade
+ * has the same N, hx and hy as then and its origin moved by whole texels
+ * (hfr_fit_cascades_aligned gives such lattices), each 16 x 16 texel block
+ * whose visible texels were all visible then copies them from prev_tex
+ * instead of evaluating Eq. 2; other blocks and cascades are computed as
+ * hfr_discretize does.  A copied texel equals the one computed at the same
+ * world position last frame, so the leaves, the basis and the domain must
+ * be unchanged since prev_tex was written (the caller's responsibility).
+ * reused: device int32 that each copied block increments (caller-zeroed),
+ * or NULL (counting costs one atomic per copied block on that one address).  EINVAL as hfr_discretize, NULL prev_cas or prev_tex,
+ * overlapping buffers. */
+hfr_status hfr_discretize_reuse(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas,
+                                int32_t K, const hfr_cascade* prev_cas, const float* prev_tex, float* tex,
+                                uint32_t* mask, int32_t* reused, hfr_stream stream);
 
 /* Maximum mipmap (Tevs et al. 2008, used in Section 5).  Level 0 is N x N
  * by texture cell: the largest of the cell's four corner texels, -inf when

@@ -92,8 +92,10 @@ SIGNATURES = {
     "hfr_neighbours_destroy": ([P], None),
     "hfr_build_level_index": ([I64, P, P, P, F64, F64, F64, I32, P, P], I32),
     "hfr_fit_cascades": ([PP(Camera), PP(Domain), I32, I32, F64, F64, F64, PP(Cascade)], I32),
+    "hfr_fit_cascades_aligned": ([PP(Camera), PP(Domain), I32, I32, F64, F64, F64, PP(Cascade)], I32),
     "hfr_pack_leaves": ([PP(Leaves), P], I32),
     "hfr_discretize": ([PP(Leaves), PP(Domain), PP(Cascade), I32, P, P, P], I32),
+    "hfr_discretize_reuse": ([PP(Leaves), PP(Domain), PP(Cascade), I32, PP(Cascade), P, P, P, P, P], I32),
     "hfr_build_maxmip": ([P, I32, I32, P, P], I32),
     "hfr_raycast": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
     "hfr_raycast_backward": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),

@@ -196,9 +196,12 @@ def build_level_index(leaves: dict, side: float, max_depth: int, x0: float = 0.0
     return rank, order
 
 
-def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: float) -> ctypes.Array:
+def fit_cascades(cam, dom, K: int, N: int, lam: float, overlap: float, c_min: float,
+                 aligned: bool = False) -> ctypes.Array:
+    """Cascades of one camera; ``aligned``: texel lattices fixed in the world (hfr_fit_cascades_aligned)."""
     out = (Cascade * K)()
-    call("hfr_fit_cascades", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), K, N, lam, overlap, c_min, out)
+    call("hfr_fit_cascades_aligned" if aligned else "hfr_fit_cascades", ctypes.byref(camera(cam)),
+         ctypes.byref(domain(dom)), K, N, lam, overlap, c_min, out)
     return out
 
 
@@ -305,6 +308,26 @@ def discretize(L: DeviceLeaves, dom, cascades: ctypes.Array, tex=None, mask=None
     mp = _dev(mask, torch.int32, (K, N, (N + 31) // 32), "mask") if mask is not None else None
     call("hfr_discretize", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, tp, mp,
          _stream(stream))
+    return tex
+
+
+def discretize_reuse(L: DeviceLeaves, dom, cascades: ctypes.Array, prev_cascades: ctypes.Array, prev_tex, tex=None,
+                     mask=None, reused=None, stream=None):
+    """``discretize`` for the next frame, copying the blocks whose texels the previous frame already
+    holds (``prev_cascades``, ``prev_tex``; same leaves).  ``reused``: int32 device tensor [1] that
+    counts the copied 16 x 16 blocks (caller-zeroed), or None."""
+    import torch
+    K, N = len(cascades), cascades[0].n
+    if len(prev_cascades) != K:
+        raise ValueError("prev_cascades must hold one cascade per cascade")
+    if tex is None:
+        tex = torch.empty((K, N, N), dtype=torch.float32, device=L.x.device)
+    tp = _dev(tex, torch.float32, (K, N, N), "tex")
+    pp = _dev(prev_tex, torch.float32, (K, N, N), "prev_tex")
+    mp = _dev(mask, torch.int32, (K, N, (N + 31) // 32), "mask") if mask is not None else None
+    rp = _dev(reused, torch.int32, (1,), "reused") if reused is not None else None
+    call("hfr_discretize_reuse", ctypes.byref(L.struct()), ctypes.byref(domain(dom)), cascades, K, prev_cascades, pp,
+         tp, mp, rp, _stream(stream))
     return tex
 
 

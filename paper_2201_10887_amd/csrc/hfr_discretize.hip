@@ -387,6 +387,13 @@ __device__ inline TileFrame tile_frame(const TexCascade& C, const Dom2& D, const
     return f;
 }
 
+// The previous frame's texture of a cascade on the same lattice: texel (i, j)
+// now is texel (i + di, j + dj) then.  prev == nullptr: nothing to reuse.
+struct Reuse {
+    const float* prev;
+    int di, dj;
+};
+
 struct DiscShared {
     float4 brec[BCAP];
     float4 trec_all[WAVES][TCAP];
@@ -400,7 +407,8 @@ struct DiscShared {
 // takes part.
 template <int BASIS>
 __device__ __forceinline__ void discretize_block(const Tables& T, const TexCascade& C, const Dom2& D, int bx, int by,
-                                                 float* __restrict__ tex, uint16_t* __restrict__ mask, DiscShared& sh)
+                                                 float* __restrict__ tex, uint16_t* __restrict__ mask, DiscShared& sh,
+                                                 const Reuse* ru = nullptr, int* reused = nullptr)
 {
     float4* brec = sh.brec;
     int& any_vis = sh.any_vis;
@@ -418,6 +426,17 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     if (!any_vis) {
         if (inside) tex[(int64_t)j * N + i] = -INFINITY;
         return;
+    }
+    if (ru != nullptr && ru->prev != nullptr) {
+        // copy the block when every texel visible now was computed last frame
+        const int pi = i + ru->di, pj = j + ru->dj;
+        float old = -INFINITY;
+        if (vis && pi >= 0 && pi < N && pj >= 0 && pj < N) old = ru->prev[(int64_t)pj * N + pi];
+        if (__syncthreads_and(!vis || isfinite(old))) {
+            if (inside) tex[(int64_t)j * N + i] = vis ? old : -INFINITY;
+            if (reused != nullptr && threadIdx.x == 0) atomicAdd(reused, 1);
+            return;
+        }
     }
     const Rect br = texel_rect(C, D, bi0, bj0, BS, BS);
     const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j);
@@ -489,6 +508,8 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
 constexpr int FUSE = 4;
 struct CascadeSet {
     TexCascade c[FUSE];
+    Reuse r[FUSE];
+    int* reused;  // blocks copied from the previous frame (may be nullptr)
     int K;
 };
 
@@ -512,7 +533,7 @@ __global__ __launch_bounds__(256, 8) void discretize_kernel(Tables T, CascadeSet
     const TexCascade& C = S.c[k];
     const int64_t N = C.n;
     discretize_block<BASIS>(T, C, D, bx, by, tex + k * N * N, mask ? mask + k * N * 2 * ((N + 31) / 32) : nullptr,
-                            sh);
+                            sh, &S.r[k], S.reused);
 }
 
 // Adjoint of Eq. 2 / Eq. 1.  Lanes first own texels (S0 of each texel), then
@@ -748,8 +769,25 @@ extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
     return hfr_ok();
 }
 
-extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
-                                     float* tex, uint32_t* mask, hfr_stream stream)
+namespace {
+
+// Whole-texel shift from the previous frame's lattice of a cascade to this one's, when both
+// frames use the same spacing and the lattices coincide; false otherwise.
+bool lattice_shift(const hfr_cascade& now, const hfr_cascade& then, int* di, int* dj)
+{
+    if (then.n != now.n || then.hx != now.hx || then.hy != now.hy || then.n_poly == 0 || now.n_poly == 0) return false;
+    const double sx = (now.x0 - then.x0) / now.hx, sy = (now.y0 - then.y0) / now.hy;
+    if (!(std::fabs(sx) < now.n && std::fabs(sy) < now.n)) return false;
+    const double rx = std::nearbyint(sx), ry = std::nearbyint(sy);
+    if (std::fabs(sx - rx) > 1e-6 || std::fabs(sy - ry) > 1e-6) return false;
+    *di = (int)rx;
+    *dj = (int)ry;
+    return true;
+}
+
+hfr_status discretize_frame(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
+                            const hfr_cascade* prev_cas, const float* prev_tex, float* tex, uint32_t* mask,
+                            int32_t* reused, hfr_stream stream)
 {
     Tables T;
     hfr_status st = leaf_tables(L, false, &T);
@@ -758,13 +796,25 @@ extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom,
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex != nullptr, "tex is NULL");
     const int N = cas[0].n;
+    const int64_t texels = (int64_t)K * N * N;
+    if (prev_cas != nullptr) {
+        HFR_REQUIRE(prev_tex != nullptr, "prev_tex is NULL");
+        HFR_REQUIRE(prev_tex + texels <= tex || tex + texels <= prev_tex, "prev_tex overlaps tex");
+    }
     const Dom2 D{dom->x0, dom->y0, dom->x1, dom->y1};
     const int gx = (N + BS - 1) / BS, gy = (N + BS - 1) / BS;
     const int words = (N + 31) / 32;
     for (int k0 = 0; k0 < K; k0 += FUSE) {
         CascadeSet S;
         S.K = std::min(FUSE, K - k0);
-        for (int k = 0; k < S.K; ++k) S.c[k] = tex_cascade(cas[k0 + k]);
+        S.reused = reused;
+        for (int k = 0; k < S.K; ++k) {
+            S.c[k] = tex_cascade(cas[k0 + k]);
+            S.r[k] = Reuse{nullptr, 0, 0};
+            int di = 0, dj = 0;
+            if (prev_cas != nullptr && lattice_shift(cas[k0 + k], prev_cas[k0 + k], &di, &dj))
+                S.r[k] = Reuse{prev_tex + (int64_t)(k0 + k) * N * N, di, dj};
+        }
         float* t = tex + (int64_t)k0 * N * N;
         uint16_t* m = mask ? reinterpret_cast<uint16_t*>(mask + (int64_t)k0 * N * words) : nullptr;
         const dim3 grid(gx * gy * S.K), block(64 * WAVES);
@@ -775,6 +825,22 @@ extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom,
         HFR_LAUNCH_CHECK("discretize");
     }
     return hfr_ok();
+}
+
+}  // namespace
+
+extern "C" hfr_status hfr_discretize(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
+                                     float* tex, uint32_t* mask, hfr_stream stream)
+{
+    return discretize_frame(L, dom, cas, K, nullptr, nullptr, tex, mask, nullptr, stream);
+}
+
+extern "C" hfr_status hfr_discretize_reuse(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas,
+                                           int32_t K, const hfr_cascade* prev_cas, const float* prev_tex, float* tex,
+                                           uint32_t* mask, int32_t* reused, hfr_stream stream)
+{
+    HFR_REQUIRE(prev_cas != nullptr, "prev_cas is NULL (use hfr_discretize for a first frame)");
+    return discretize_frame(L, dom, cas, K, prev_cas, prev_tex, tex, mask, reused, stream);
 }
 
 extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom, const hfr_cascade* cas,

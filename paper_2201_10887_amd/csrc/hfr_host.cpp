@@ -476,10 +476,42 @@ void snap_axis(double lo, double hi, double origin, double c_min, int N, double*
     *h = ext / (N - 1);
 }
 
+// Fixed-lattice form: the spacing is the smallest c_min 2^(e/4) (integer e) whose lattice,
+// anchored at a whole number of spacings from the origin, covers [lo, hi].
+void snap_axis_aligned(double lo, double hi, double origin, double c_min, int N, double* x0, double* h)
+{
+    static const double quarter[4] = {1.0, 1.189207115002721, 1.4142135623730951, 1.681792830507429};
+    const double need = std::max(hi - lo, 0.0) / (N - 1);
+    int e = need > 0 ? (int)std::floor(4.0 * std::log2(need / c_min)) - 1 : -64;
+    for (;; ++e) {
+        const int q = (int)std::floor(e / 4.0), r = e - 4 * q;
+        *h = std::ldexp(c_min * quarter[r], q);
+        *x0 = origin + std::floor((lo - origin) / *h + kSnapTol) * *h;
+        if (*x0 + (N - 1) * *h >= hi - kSnapTol * *h) return;
+    }
+}
+
+hfr_status fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N, double lambda,
+                        double overlap, double c_min, bool aligned, hfr_cascade* out);
+
 }  // namespace
 
 extern "C" hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N,
                                        double lambda, double overlap, double c_min, hfr_cascade* out)
+{
+    return fit_cascades(cam, dom, K, N, lambda, overlap, c_min, false, out);
+}
+
+extern "C" hfr_status hfr_fit_cascades_aligned(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N,
+                                               double lambda, double overlap, double c_min, hfr_cascade* out)
+{
+    return fit_cascades(cam, dom, K, N, lambda, overlap, c_min, true, out);
+}
+
+namespace {
+
+hfr_status fit_cascades(const hfr_camera* cam, const hfr_domain* dom, int32_t K, int32_t N, double lambda,
+                        double overlap, double c_min, bool aligned, hfr_cascade* out)
 {
     HFR_REQUIRE(cam && dom && out, "NULL argument");
     HFR_REQUIRE(K >= 1 && K <= HFR_MAX_CASCADES, "K = %d outside [1, %d]", K, HFR_MAX_CASCADES);
@@ -591,8 +623,11 @@ extern "C" hfr_status hfr_fit_cascades(const hfr_camera* cam, const hfr_domain* 
             ymin = std::min(ymin, poly[a].y);
             ymax = std::max(ymax, poly[a].y);
         }
-        snap_axis(xmin, xmax, dom->x0, c_min, N, &c.x0, &c.hx);
-        snap_axis(ymin, ymax, dom->y0, c_min, N, &c.y0, &c.hy);
+        auto snap = aligned ? snap_axis_aligned : snap_axis;
+        snap(xmin, xmax, dom->x0, c_min, N, &c.x0, &c.hx);
+        snap(ymin, ymax, dom->y0, c_min, N, &c.y0, &c.hy);
     }
     return hfr_ok();
 }
+
+}  // namespace

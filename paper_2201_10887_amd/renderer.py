@@ -64,6 +64,15 @@ class Renderer:
         self.long_ray_queue_backward = True
         self._work = {}
         self.extra = []  # further surfaces on the same cells (add_surface)
+        # frame-to-frame texel reuse (set_texel_reuse): fixed-lattice cascades, a second texture set
+        # per surface, the previous frame's cascades (None: nothing to reuse)
+        self.texel_reuse = False
+        self._spare = []
+        self._prev_cas = None
+        # count copied blocks into reused_blocks (one atomic per copied block on a single address:
+        # measurable, so off unless asked for)
+        self.count_reused = False
+        self.reused_blocks = torch.zeros(1, dtype=torch.int32, device=device)
 
     def ray_work(self, cam, backward: bool = False):
         """The long-ray queue for this camera's image size (None when disabled)."""
@@ -119,10 +128,22 @@ class Renderer:
         return self.dom
 
     def fit(self, cam):
-        return api.fit_cascades(cam, self.dom, self.K, self.N, self.lam, self.overlap, self.c_min)
+        return api.fit_cascades(cam, self.dom, self.K, self.N, self.lam, self.overlap, self.c_min,
+                                aligned=self.texel_reuse)
+
+    def set_texel_reuse(self, on: bool = True):
+        """Frame-to-frame texel reuse along a camera path: cascades fitted on lattices fixed in the world
+        (``fit_cascades(..., aligned=True)``) and each frame's textures written into a second buffer,
+        copying the 16 x 16 blocks the previous frame already holds (``discretize_reuse``).  Changing
+        the leaves (``refresh_leaves``) or adding a surface forgets the previous frame."""
+        import torch
+        self.texel_reuse = bool(on)
+        self._prev_cas = None
+        self._spare = [torch.empty_like(tex) for _, tex, _, _ in self.surfaces()] if on else []
 
     def refresh_leaves(self, stream=None):
         """Re-derive the packed leaf records after ``L.v`` or ``L.sigma`` changed."""
+        self._prev_cas = None
         api.pack_leaves(self.L, stream)
         for surf in self.extra:
             api.pack_leaves(surf["L"], stream)
@@ -140,6 +161,9 @@ class Renderer:
         d = self.dom
         self.dom = api.domain(_Dom(d.x0, d.y0, d.x1, d.y1, min(d.zmin, float(np.min(v))), max(d.zmax, float(np.max(v)))))
         K, N = self.K, self.N
+        self._prev_cas = None
+        if self.texel_reuse:
+            self._spare.append(torch.empty_like(self.tex))
         self.extra.append({"L": L, "tex": torch.empty_like(self.tex), "mask": torch.empty_like(self.mask),
                            "mip": torch.empty_like(self.mip), "grad_tex": torch.zeros_like(self.tex),
                            "grad_v": torch.zeros(L.n, dtype=torch.float32, device=self.device)})
@@ -153,9 +177,22 @@ class Renderer:
 
     def forward(self, cam, cascades=None, depth=None, hit=None, stream=None):
         cas = self.fit(cam) if cascades is None else cascades
-        for L, tex, mask, mip in self.surfaces():
-            api.discretize(L, self.dom, cas, tex, mask, stream)
+        for s, (L, tex, mask, mip) in enumerate(self.surfaces()):
+            if self.texel_reuse and self._prev_cas is not None:
+                new = self._spare[s]
+                api.discretize_reuse(L, self.dom, cas, self._prev_cas, tex, new, mask,
+                                     self.reused_blocks if self.count_reused else None, stream)
+                self._spare[s] = tex
+                if s == 0:
+                    self.tex = new
+                else:
+                    self.extra[s - 1]["tex"] = new
+                tex = new
+            else:
+                api.discretize(L, self.dom, cas, tex, mask, stream)
             api.build_maxmip(tex, mip, stream)
+        if self.texel_reuse:
+            self._prev_cas = cas
         work = self.ray_work(cam)
         depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream, work)
         for s, surf in enumerate(self.extra, start=1):

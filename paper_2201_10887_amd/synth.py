@@ -245,6 +245,23 @@ def camera_of(w: Workload, dem: np.ndarray, width: Optional[int] = None,
                   vfov=math.radians(w.vfov_deg), width=width or w.width, height=height or w.height)
 
 
+def camera_path(cam: Camera, frames: int, step: float, yaw_step_deg: float = 0.0,
+                climb: float = 0.0) -> List[Camera]:
+    """A flight: ``frames`` poses starting at ``cam``, each ``step`` metres further along the horizontal
+    view direction (and ``climb`` metres up), turning by ``yaw_step_deg`` per frame."""
+    out = []
+    x, y, z = cam.pos
+    yaw = cam.yaw
+    for _ in range(frames):
+        out.append(Camera(pos=(x, y, z), yaw=yaw, pitch=cam.pitch, vfov=cam.vfov, width=cam.width,
+                          height=cam.height))
+        x += step * math.sin(yaw)
+        y += step * math.cos(yaw)
+        z += climb
+        yaw += math.radians(yaw_step_deg)
+    return out
+
+
 def random_cameras(dem: np.ndarray, side: float, count: int, seed: int,
                    sizes: List[Tuple[int, int]]) -> List[Camera]:
     """Random poses above the terrain: xy in the inner 80 %, 50-500 m up, pitch -30..-3 deg."""

@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 8
+    assert api.abi_version() == 9
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -157,6 +157,20 @@ def test_fit_cascades_matches_oracle(pos, yaw, pitch, K, N, lam):
         _compare_cascades(a, b, dom.extent)
 
 
+@pytest.mark.parametrize("pos,yaw,pitch", CAMERAS)
+@pytest.mark.parametrize("K,N,lam", [(2, 256, 1.0), (4, 2048, 0.5)])
+def test_aligned_fit_matches_oracle(pos, yaw, pitch, K, N, lam):
+    dom = synth.Domain(0.0, 0.0, 1024.0, 1024.0, 5.0, 300.0)
+    cam = synth.Camera(pos=pos, yaw=math.radians(yaw), pitch=math.radians(pitch), vfov=math.radians(60.0),
+                       width=320, height=180)
+    got = [api.CascadeView(c) for c in api.fit_cascades(cam, dom, K, N, lam, 0.05, 16.0, aligned=True)]
+    ref = ocas.fit_cascades(cam, dom, K, N, lam, 0.05, 16.0, aligned=True)
+    for a, b in zip(got, ref):
+        _compare_cascades(a, b, dom.extent)
+        if len(b.poly):  # the ladder step itself is a decision: equal, not merely close
+            assert a.hx == b.hx and a.hy == b.hy
+
+
 def test_fit_cascades_c2_scene():
     dem = synth.fbm_dem(256, 8, 0.8, 1)
     w = synth.MEDIUM
@@ -215,6 +229,14 @@ def test_invalid_arguments_rejected_before_launch():
     _raise_einval("hfr_discretize_backward", ctypes.byref(L3), ctypes.byref(dom), cs, 2, dummy, dummy, dummy,
                   dummy, None)
     _raise_einval("hfr_pack_leaves", ctypes.byref(api.Leaves()), None)
+    # reuse: no previous frame, or previous textures overlapping the output
+    _raise_einval("hfr_discretize_reuse", ctypes.byref(L), ctypes.byref(dom), cs, 2, None, dummy, dummy, None, None,
+                  None)
+    L5 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 3.5, 0.0, 0.0, 1.0)
+    _raise_einval("hfr_discretize_reuse", ctypes.byref(L5), ctypes.byref(dom), cs, 2, cs, None, dummy, None, None,
+                  None)
+    _raise_einval("hfr_discretize_reuse", ctypes.byref(L5), ctypes.byref(dom), cs, 2, cs, ctypes.c_void_p(0x1004),
+                  dummy, None, None, None)
     # unknown basis
     L4 = api.Leaves(10, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 4, 3.5, 0.0, 0.0, 1.0, 2)
     _raise_einval("hfr_pack_leaves", ctypes.byref(L4), None)
@@ -232,7 +254,7 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 8
+    assert lib.hfr_abi_version() == 9
 
 
 def test_batch_arguments_rejected_before_any_device_call():

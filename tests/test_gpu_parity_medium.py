@@ -90,6 +90,36 @@ def test_wendland_discretize_sampled(gpu, medium):
     del W
 
 
+def test_texel_reuse_next_frame_sampled(gpu, medium):
+    """The next frame of a flight built by copying blocks of this one: sampled texels of all four
+    cascades against the oracle, and blocks copied."""
+    m = medium
+    w = m["w"]
+    c_min = float(m["leaves"]["c"].min())
+    cams = synth.camera_path(m["cam"], 2, step=2.0, yaw_step_deg=0.05)
+    cas0, cas1 = (api.fit_cascades(c, m["dom"], w.cascades, w.tex_n, w.split_lambda, w.overlap, c_min, aligned=True)
+                  for c in cams)
+    tex0 = api.discretize(m["L"], m["dom"], cas0)
+    reused = gpu.zeros(1, dtype=gpu.int32, device="cuda")
+    tex = api.discretize_reuse(m["L"], m["dom"], cas1, cas0, tex0, reused=reused).cpu().numpy()
+    del tex0
+    field = odisc.RBFField(m["leaves"], w.cutoff)
+    rng = np.random.default_rng(2026)
+    blocks = 0
+    for k, c in enumerate(cas1):
+        cv = api.CascadeView(c)
+        vis = odisc.visibility(cv)
+        assert np.array_equal(vis, np.isfinite(tex[k]))
+        blocks += int(vis.reshape(vis.shape[0] // 16, 16, -1, 16).any(axis=(1, 3)).sum())
+        jj, ii = np.nonzero(vis)
+        pick = rng.choice(len(jj), 2000, replace=False)
+        ref, _ = field.evaluate(odisc.clamp_to_domain(odisc.texel_centres(cv, ii[pick], jj[pick]), m["dom"]))
+        err = np.abs(tex[k][jj[pick], ii[pick]] - ref)
+        assert np.all(err <= G.texel_tolerance(m["leaves"], ref)), (k, err.max())
+    print(f"copied {int(reused.item())} of {blocks} visible blocks", flush=True)
+    assert int(reused.item()) > 0
+
+
 def test_discretize_full_frame_sampled(gpu, medium):
     m = medium
     K, N = len(m["cas"]), m["cas"][0].n
