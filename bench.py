@@ -407,6 +407,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--skip-flight", action="store_true",
+                    help="skip the texel-reuse flight (profiled runs: its launches differ from a frame's)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (known traffic) to calibrate hardware byte counters")
     args = ap.parse_args()
@@ -502,7 +504,7 @@ def main():
 
     startup = startup_ms(R, dem, w)
     work = discretize_work(R, cas, leaves, w)
-    reuse = texel_reuse_flight(R, cam, depth, hit)
+    reuse = None if args.skip_flight else texel_reuse_flight(R, cam, depth, hit)
     print(f"[bench] texel reuse along a flight: {reuse}", file=sys.stderr, flush=True)
     vis_texels, pairs = work["visible_texels"], work["pairs"]
     forward()  # leave the full frame (every surface) in depth / hit
