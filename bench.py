@@ -68,7 +68,8 @@ def build_scene(name: str):
 
 def startup_ms(R, dem, w) -> dict:
     """Start-up costs: the quadtree on the host and on the device (the raster already resident,
-    the leaf count read back once), and the host level index."""
+    the leaf count read back once), the host level index, and the per-leaf influence lists on the
+    device and (while their offsets fit 32 bits) on the host."""
     import torch
     from paper_2201_10887_amd import api
     d = torch.as_tensor(np.ascontiguousarray(dem, np.float32), device="cuda")
@@ -80,14 +81,33 @@ def startup_ms(R, dem, w) -> dict:
     t_dev = (time.perf_counter() - t0) * 1e3
     if q["x"].numel() != R.L.n:
         raise RuntimeError("device and host quadtrees differ in leaf count")
+    # the paper's per-leaf influence lists, on the device over the device-built leaves
+    Lq = api.DeviceLeaves.from_device(q, w.sigma, w.side, w.max_depth, w.cutoff)
+    api.pack_leaves(Lq)
     del q, d
+    off, idx = api.build_neighbours_device(Lq)
+    del off, idx
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    off, idx = api.build_neighbours_device(Lq)
+    torch.cuda.synchronize()
+    t_nb = (time.perf_counter() - t0) * 1e3
+    nnz = int(idx.numel())
+    del off, idx, Lq
     leaves = {"x": R.L.x.cpu().numpy(), "y": R.L.y.cpu().numpy(), "c": R.L.c.cpu().numpy()}
     t0 = time.perf_counter()
     api.build_level_index(leaves, w.side, w.max_depth)
     t_index = (time.perf_counter() - t0) * 1e3
     torch.cuda.empty_cache()
-    return {"quadtree_host": round(build_scene.quadtree_host_ms, 1), "quadtree_device": round(t_dev, 2),
-            "level_index_host": round(t_index, 1)}
+    out = {"quadtree_host": round(build_scene.quadtree_host_ms, 1), "quadtree_device": round(t_dev, 2),
+           "level_index_host": round(t_index, 1), "neighbours_device": round(t_nb, 2), "neighbour_entries": nnz}
+    if nnz < 2 ** 31:  # the host lists use 32-bit offsets
+        leaves["sigma"] = np.full(len(leaves["x"]), w.sigma, np.float32)
+        t0 = time.perf_counter()
+        api.build_neighbours(leaves, w.side, w.max_depth, w.cutoff)
+        out["neighbours_host"] = round((time.perf_counter() - t0) * 1e3, 1)
+        out["neighbours_host_threads"] = min(os.cpu_count() or 1, 64)
+    return out
 
 
 def texel_reuse_flight(R, cam, depth, hit, frames=32, step=2.0, yaw_step=0.05) -> dict:

@@ -210,6 +210,27 @@ hfr_status hfr_quadtree_device_leaves(int64_t n, double side, double x0, double 
                                       float* y, float* c, float* v, int32_t* level, int32_t* i, int32_t* j,
                                       hfr_stream stream);
 
+/* The per-leaf lists of hfr_build_neighbours built on the device, for leaves
+ * already on the device with their level index and level radii (L->x, y, c,
+ * sigma, rank, order, level_radius after hfr_pack_leaves; L->v and
+ * L->packed are not read).  Lists are indexed by sorted position: list p
+ * belongs to leaf order[p] and holds the sorted positions q (ascending) of
+ * the leaves order[q] in it, under the same FP64 test as
+ * hfr_build_neighbours.  For leaves from hfr_quadtree_device_leaves (order =
+ * 0 .. n-1) positions are leaf indices and the lists equal
+ * hfr_build_neighbours' lists of the same leaves.  Two calls:
+ * hfr_build_neighbours_device writes off (device int64[n + 1], CSR offsets)
+ * and returns the entry count (it synchronizes the stream to read it), using
+ * work (device scratch of hfr_neighbours_device_workspace bytes);
+ * hfr_neighbours_device_fill then writes idx (device int32[nnz]).  The
+ * caller owns every buffer.  EINVAL: NULL pointers, n outside
+ * [1, INT32_MAX], max_depth outside [0, 15], cutoff <= 0, slack < 0. */
+hfr_status hfr_neighbours_device_workspace(int64_t n, int64_t* bytes);
+hfr_status hfr_build_neighbours_device(const hfr_leaves* L, float slack, void* work, int64_t* off, int64_t* nnz,
+                                       hfr_stream stream);
+hfr_status hfr_neighbours_device_fill(const hfr_leaves* L, float slack, const int64_t* off, int32_t* idx,
+                                      hfr_stream stream);
+
 /* Level index of the leaves (host arrays).  Leaves are ordered by level,
  * then lattice row j (y), then column i (x): order[p] is the leaf at sorted
  * position p (int32[n]).  rank holds, for every level l, 4^l + 1 exclusive

@@ -100,6 +100,9 @@ SIGNATURES = {
     "hfr_raycast": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
     "hfr_raycast_backward": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
     "hfr_quadtree_device_workspace": ([I64, I32, PP(I64)], I32),
+    "hfr_neighbours_device_workspace": ([I64, PP(I64)], I32),
+    "hfr_build_neighbours_device": ([PP(Leaves), F32, P, P, PP(I64), P], I32),
+    "hfr_neighbours_device_fill": ([PP(Leaves), F32, P, P, P], I32),
     "hfr_build_quadtree_device": ([P, I64, F64, F64, F64, I32, F64, P, P, PP(I64), P], I32),
     "hfr_quadtree_device_leaves": ([I64, F64, F64, F64, I32, P, P, I64, P, P, P, P, P, P, P, P], I32),
     "hfr_raycast_nearer": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, I32, P, P, P, P], I32),

@@ -145,6 +145,25 @@ def build_quadtree_device(dem, side: float, max_depth: int, tau: float, x0: floa
     return out
 
 
+def build_neighbours_device(L: "DeviceLeaves", slack: float = 1e-3, stream=None) -> tuple:
+    """``build_neighbours`` on the device for packed ``DeviceLeaves`` (level radii written): device
+    tensors ``(off int64[n + 1], idx int32[nnz])`` indexed by sorted position (leaf indices for leaves
+    from ``build_quadtree_device``)."""
+    import torch
+    dev = L.x.device
+    nbytes = ctypes.c_int64()
+    call("hfr_neighbours_device_workspace", L.n, ctypes.byref(nbytes))
+    work = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=dev)
+    off = torch.empty(L.n + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64()
+    Ls = L.struct()
+    call("hfr_build_neighbours_device", ctypes.byref(Ls), slack, work.data_ptr(), off.data_ptr(), ctypes.byref(nnz),
+         _stream(stream))
+    idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    call("hfr_neighbours_device_fill", ctypes.byref(Ls), slack, off.data_ptr(), idx.data_ptr(), _stream(stream))
+    return off, idx[:nnz.value]
+
+
 def quadtree_leaf_count(dem: np.ndarray, side: float, max_depth: int, tau: float) -> int:
     """Leaf count of ``build_quadtree`` without exporting the leaves."""
     dem = np.ascontiguousarray(dem, np.float32)

@@ -22,8 +22,8 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
-inline int64_t pyramid_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
-inline int64_t rank_offset(int l) { return pyramid_offset(l) + l; }
+__host__ __device__ inline int64_t pyramid_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+__host__ __device__ inline int64_t rank_offset(int l) { return pyramid_offset(l) + l; }
 
 __global__ void raster_to_double_kernel(const float* __restrict__ dem, double* __restrict__ out, int64_t count)
 {
@@ -92,11 +92,11 @@ __global__ void leaf_flags_kernel(int l, int max_depth, const uint8_t* __restric
 
 // In-place inclusive scan of each SCAN_TILE-element tile; the tile's total
 // goes to sums[tile].
-__global__ __launch_bounds__(SCAN_THREADS) void scan_tiles_kernel(int32_t* __restrict__ data, int64_t n,
-                                                                  int32_t* __restrict__ sums)
+template <typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void scan_tiles_kernel(T* __restrict__ data, int64_t n, T* __restrict__ sums)
 {
-    __shared__ int32_t buf[SCAN_TILE];
-    __shared__ int32_t wsum[SCAN_THREADS / 64];
+    __shared__ T buf[SCAN_TILE];
+    __shared__ T wsum[SCAN_THREADS / 64];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -104,19 +104,19 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_tiles_kernel(int32_t* __res
         buf[e] = base + e < n ? data[base + e] : 0;
     }
     __syncthreads();
-    int32_t run = 0;
+    T run = 0;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         run += buf[t * SCAN_ITEMS + k];
         buf[t * SCAN_ITEMS + k] = run;
     }
-    int32_t incl = run;
+    T incl = run;
     for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o);
+        const T y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int32_t before = incl - run;
+    T before = incl - run;
     for (int w = 0; w < wave; ++w) before += wsum[w];
     for (int k = 0; k < SCAN_ITEMS; ++k) buf[t * SCAN_ITEMS + k] += before;
     __syncthreads();
@@ -128,10 +128,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_tiles_kernel(int32_t* __res
 }
 
 // Adds the inclusive prefix of the earlier tiles' totals to every tile but the first.
-__global__ void add_tile_offsets_kernel(int32_t* __restrict__ data, int64_t n, const int32_t* __restrict__ sums)
+template <typename T>
+__global__ void add_tile_offsets_kernel(T* __restrict__ data, int64_t n, const T* __restrict__ sums)
 {
     const int64_t tile = (int64_t)blockIdx.x + 1;
-    const int32_t add = sums[tile - 1];
+    const T add = sums[tile - 1];
     for (int64_t e = tile * SCAN_TILE + threadIdx.x; e < std::min<int64_t>(n, (tile + 1) * SCAN_TILE);
          e += blockDim.x)
         data[e] += add;
@@ -157,6 +158,60 @@ __global__ void emit_leaves_kernel(int l, double side, double x0, double y0, con
         if (level) level[p] = l;
         if (li) li[p] = (int32_t)ii;
         if (lj) lj[p] = (int32_t)jj;
+    }
+}
+
+// Per-leaf lists of the leaves whose truncation radius (widened by slack)
+// reaches the leaf's closed square, in level-index (sorted position) space:
+// thread p handles the leaf at sorted position p and walks, level by level,
+// the window rows around its square through the rank table, testing each
+// leaf there exactly as hfr_build_neighbours does (FP64, unfused).  With
+// FILL = false it writes the list length to counts[p + 1]; with FILL = true
+// it writes the sorted positions of the list from off[p] on.
+template <bool FILL>
+__global__ void neighbours_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                                  const float* __restrict__ c, const float* __restrict__ sigma,
+                                  const int32_t* __restrict__ rank, const int32_t* __restrict__ order,
+                                  const float* __restrict__ level_radius, int64_t n, int max_depth, double cutoff,
+                                  double widen, double x0, double y0, double side, int64_t* __restrict__ off,
+                                  int32_t* __restrict__ idx)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = order[p];
+        const double xa = x[a], ya = y[a], ha = __dmul_rn(0.5, (double)c[a]);
+        int64_t k = 0, base = 0, cap = 0;
+        if (FILL) {
+            base = off[p];
+            cap = off[p + 1] - base;
+        }
+        for (int l = 0; l <= max_depth; ++l) {
+            const double Rl = (double)level_radius[l];
+            if (!(Rl > 0.0)) continue;
+            const int64_t S = int64_t(1) << l;
+            const double cl = ldexp(side, -l);
+            const double reach = ha + Rl * widen;
+            const int64_t i0 = max((int64_t)0, (int64_t)floor((xa - reach - x0) / cl - 0.5) - 1);
+            const int64_t i1 = min(S - 1, (int64_t)ceil((xa + reach - x0) / cl - 0.5) + 1);
+            const int64_t j0 = max((int64_t)0, (int64_t)floor((ya - reach - y0) / cl - 0.5) - 1);
+            const int64_t j1 = min(S - 1, (int64_t)ceil((ya + reach - y0) / cl - 0.5) + 1);
+            if (i0 > i1 || j0 > j1) continue;
+            const int32_t* rk = rank + rank_offset(l);
+            for (int64_t jj = j0; jj <= j1; ++jj) {
+                const int32_t lo = rk[jj * S + i0], hi = rk[jj * S + i1 + 1];
+                for (int32_t q = lo; q < hi; ++q) {
+                    const int32_t b = order[q];
+                    const double dx = fmax(__dsub_rn(fabs(__dsub_rn((double)x[b], xa)), ha), 0.0);
+                    const double dy = fmax(__dsub_rn(fabs(__dsub_rn((double)y[b], ya)), ha), 0.0);
+                    const double R = __dmul_rn(__dmul_rn(__dmul_rn(cutoff, (double)sigma[b]), (double)c[b]), widen);
+                    if (__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) < __dmul_rn(R, R)) {
+                        if (FILL && k < cap) idx[base + k] = q;
+                        ++k;
+                    }
+                }
+            }
+        }
+        if (!FILL) off[p + 1] = k;
+        if (!FILL && p == 0) off[0] = 0;
     }
 }
 
@@ -193,13 +248,14 @@ Layout layout_of(int D, int max_depth)
 int grid_for(int64_t count) { return (int)std::min<int64_t>((count + 255) / 256, 8192); }
 
 // Inclusive scan of data[0, n) in place; sums has scan_sums_count(n) entries.
-void scan_inclusive(int32_t* data, int64_t n, int32_t* sums, hipStream_t s)
+template <typename T>
+void scan_inclusive(T* data, int64_t n, T* sums, hipStream_t s)
 {
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    scan_tiles_kernel<<<dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s>>>(data, n, sums);
+    scan_tiles_kernel<T><<<dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s>>>(data, n, sums);
     if (tiles > 1) {
-        scan_inclusive(sums, tiles, sums + tiles, s);
-        add_tile_offsets_kernel<<<dim3((unsigned)(tiles - 1)), dim3(256), 0, s>>>(data, n, sums);
+        scan_inclusive<T>(sums, tiles, sums + tiles, s);
+        add_tile_offsets_kernel<T><<<dim3((unsigned)(tiles - 1)), dim3(256), 0, s>>>(data, n, sums);
     }
 }
 
@@ -261,7 +317,7 @@ extern "C" hfr_status hfr_build_quadtree_device(const float* dem, int64_t n, dou
             present + pyramid_offset(l), rank + rank_offset(l));
     }
     const int64_t total = rank_offset(max_depth + 1);
-    scan_inclusive(rank, total, sums, s);
+    scan_inclusive<int32_t>(rank, total, sums, s);
     HFR_LAUNCH_CHECK("build_quadtree_device");
     int32_t count = 0;
     HFR_REQUIRE(hipMemcpyAsync(&count, rank + total - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
@@ -292,5 +348,67 @@ extern "C" hfr_status hfr_quadtree_device_leaves(int64_t n, double side, double 
                                                                        n_leaves);
     }
     HFR_LAUNCH_CHECK("quadtree_device_leaves");
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_neighbours_device_workspace(int64_t n, int64_t* bytes)
+{
+    HFR_REQUIRE(bytes != nullptr, "bytes is NULL");
+    HFR_REQUIRE(n >= 1 && n <= INT32_MAX, "leaf count %lld outside [1, INT32_MAX]", (long long)n);
+    *bytes = scan_sums_count(n + 1) * (int64_t)sizeof(int64_t);
+    return hfr_ok();
+}
+
+namespace {
+
+hfr_status check_neighbour_args(const hfr_leaves* L, float slack)
+{
+    HFR_REQUIRE(L != nullptr, "leaves are NULL");
+    HFR_REQUIRE(L->n >= 1 && L->n <= INT32_MAX, "leaf count %lld outside [1, INT32_MAX]", (long long)L->n);
+    HFR_REQUIRE(L->x && L->y && L->c && L->sigma && L->rank && L->order && L->level_radius,
+                "leaf arrays, the level index and the level radii must not be NULL");
+    HFR_REQUIRE(L->max_depth >= 0 && L->max_depth <= 15, "max_depth %d outside [0, 15]", L->max_depth);
+    HFR_REQUIRE(std::isfinite(L->cutoff) && L->cutoff > 0, "cutoff must be positive");
+    HFR_REQUIRE(std::isfinite(slack) && slack >= 0, "slack must be >= 0");
+    HFR_REQUIRE(std::isfinite(L->side) && L->side > 0 && std::isfinite(L->x0) && std::isfinite(L->y0),
+                "invalid lattice square");
+    return HFR_OK;
+}
+
+}  // namespace
+
+extern "C" hfr_status hfr_build_neighbours_device(const hfr_leaves* L, float slack, void* work, int64_t* off,
+                                                  int64_t* nnz, hfr_stream stream)
+{
+    hfr_status st = check_neighbour_args(L, slack);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(work && off && nnz, "NULL workspace, offsets or count");
+    hipStream_t s = (hipStream_t)stream;
+    const double widen = 1.0 + (double)slack;
+    neighbours_kernel<false><<<grid_for(L->n), 256, 0, s>>>(L->x, L->y, L->c, L->sigma, L->rank, L->order,
+                                                             L->level_radius, L->n, L->max_depth, (double)L->cutoff,
+                                                             widen, L->x0, L->y0, L->side, off, nullptr);
+    scan_inclusive<int64_t>(off, L->n + 1, static_cast<int64_t*>(work), s);
+    HFR_LAUNCH_CHECK("build_neighbours_device");
+    int64_t total = 0;
+    HFR_REQUIRE(hipMemcpyAsync(&total, off + L->n, sizeof(int64_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess,
+                "reading the entry count failed");
+    *nnz = total;
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_neighbours_device_fill(const hfr_leaves* L, float slack, const int64_t* off, int32_t* idx,
+                                                 hfr_stream stream)
+{
+    hfr_status st = check_neighbour_args(L, slack);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(off && idx, "NULL offsets or entries");
+    hipStream_t s = (hipStream_t)stream;
+    neighbours_kernel<true><<<grid_for(L->n), 256, 0, s>>>(L->x, L->y, L->c, L->sigma, L->rank, L->order,
+                                                            L->level_radius, L->n, L->max_depth, (double)L->cutoff,
+                                                            1.0 + (double)slack, L->x0, L->y0, L->side,
+                                                            const_cast<int64_t*>(off), idx);
+    HFR_LAUNCH_CHECK("neighbours_device_fill");
     return hfr_ok();
 }

@@ -75,3 +75,20 @@ def test_renderer_from_raster_draws_the_host_built_frame(gpu, tiny_scene):
     assert gpu.equal(dd, dh)
     # hit ids name cells by (cascade, texel): the same for both
     assert gpu.equal(hd, hh)
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_device_neighbour_lists_equal_host(gpu, name):
+    """Device-built lists over device-built leaves equal the host lists of the same leaves (the host
+    lists are pinned to brute force by the oracle tests), entry for entry."""
+    w = synth.WORKLOADS[name]
+    dem = synth.fbm_dem(w.dem_n, w.octaves, w.hurst, w.seed, mountains=w.mountains)
+    q = api.build_quadtree_device(gpu.as_tensor(dem, device="cuda"), w.side, w.max_depth, w.tau)
+    L = api.DeviceLeaves.from_device(q, w.sigma, w.side, w.max_depth, w.cutoff)
+    api.pack_leaves(L)
+    off, idx = api.build_neighbours_device(L, 1e-3)
+    host = {k: q[k].cpu().numpy() for k in ("x", "y", "c")}
+    host["sigma"] = np.full(len(host["x"]), w.sigma, np.float32)
+    h_off, h_idx = api.build_neighbours(host, w.side, w.max_depth, w.cutoff, 1e-3)
+    assert np.array_equal(off.cpu().numpy(), h_off.astype(np.int64))
+    assert np.array_equal(idx.cpu().numpy(), h_idx)
