@@ -799,7 +799,9 @@ hfr_status discretize_frame(const hfr_leaves* L, const hfr_domain* dom, const hf
     const int64_t texels = (int64_t)K * N * N;
     if (prev_cas != nullptr) {
         HFR_REQUIRE(prev_tex != nullptr, "prev_tex is NULL");
-        HFR_REQUIRE(prev_tex + texels <= tex || tex + texels <= prev_tex, "prev_tex overlaps tex");
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(prev_tex), b0 = reinterpret_cast<uintptr_t>(tex);
+        const uintptr_t bytes = (uintptr_t)texels * sizeof(float);
+        HFR_REQUIRE(a0 + bytes <= b0 || b0 + bytes <= a0, "prev_tex overlaps tex");
     }
     const Dom2 D{dom->x0, dom->y0, dom->x1, dom->y1};
     const int gx = (N + BS - 1) / BS, gy = (N + BS - 1) / BS;

@@ -73,6 +73,34 @@ def test_device_quadtree_equals_oracle_at_full_size(gpu, large):
         assert np.array_equal(dev[k].cpu().numpy(), lv[k][order]), k
 
 
+def test_device_neighbour_lists_sampled_at_full_size(gpu, large):
+    """The paper's per-leaf influence lists built on the device for the 64.1M device-built leaves
+    (3.35G entries): the lists of sampled leaves (every level, plus random ones) against the oracle's
+    definition evaluated over all leaves, entry for entry."""
+    from oracle import neighbours as onb
+    w = large["w"]
+    q = api.build_quadtree_device(gpu.as_tensor(large["dem"], device="cuda"), w.side, w.max_depth, w.tau)
+    L = api.DeviceLeaves.from_device(q, w.sigma, w.side, w.max_depth, w.cutoff)
+    api.pack_leaves(L)
+    slack = float(np.float32(1e-3))  # the library takes the slack as a float
+    off, idx = api.build_neighbours_device(L, slack)
+    _say(f"{idx.numel()} list entries")
+    lv = {k: q[k].cpu().numpy() for k in ("x", "y", "c", "level")}
+    del q
+    x, y, c = (lv[k].astype(np.float64) for k in ("x", "y", "c"))
+    R = ((w.cutoff * np.float64(np.float32(w.sigma))) * c) * (1.0 + slack)
+    rng = np.random.default_rng(77)
+    picks = [int(rng.choice(np.nonzero(lv["level"] == l)[0])) for l in np.unique(lv["level"])]
+    picks += [int(p) for p in rng.choice(len(x), 8, replace=False)]
+    o = off.cpu().numpy()
+    for a in picks:
+        d2 = onb.square_distance2(x, y, x[a], y[a], 0.5 * c[a])
+        ref = np.nonzero(d2 < R * R)[0]
+        got = idx[o[a]:o[a + 1]].cpu().numpy()
+        assert np.array_equal(got, ref), (a, int(lv["level"][a]), len(got), len(ref))
+    del off, idx, L
+
+
 def _reaching(leaves, cutoff, box):
     """Indices of every leaf whose truncation radius reaches the closed box (exact test, FP64)."""
     x = leaves["x"].astype(np.float64)
