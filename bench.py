@@ -546,7 +546,7 @@ def main():
         traffic = recorded_traffic("paper_2201_10887_amd/csrc/hfr_discretize.hip",
                                    "profiles/discretize_kernel_medium_hbm_counters.md")
     launches = -(-K // DISC_CASCADES_PER_LAUNCH)  # the library discretizes up to four cascades per launch
-    roof.update({"traffic": traffic, "kernel": "discretize_kernel", "launches": launches,
+    roof.update({"traffic": traffic, "kernel": "discretize_kernel<0>", "launches": launches,
                  "per_launch_ms": round(stage_ms["discretize"] / launches, 4),
                  "algorithmic_flops_per_launch": round(work["flops"] / launches), "algorithmic_bytes_per_launch":
                  round(work["bytes"] / launches), "hbm_frac": round(t_hbm_floor / t_disc, 4),
