@@ -121,12 +121,20 @@ def test_discretize_full_frame_sampled(gpu, large):
     vis_gpu = ((bits[:, :, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(K, N, -1)[:, :, :N].astype(bool)
     assert np.array_equal(vis_gpu, np.isfinite(tex))
     assert not np.isnan(tex).any()
-    rng = np.random.default_rng(2025)
-    for k, cas in enumerate(m["cs"]):
+    for k in range(K):
         vis = m["vis"][k]
         assert np.array_equal(vis, vis_gpu[k]), f"cascade {k}: {np.argwhere(vis != vis_gpu[k])[:5]}"
+    _check_windows(m, m["cs"], m["vis"], tex, np.random.default_rng(2025))
+
+
+def _check_windows(m, cascades, vis_all, tex, rng, basis="gaussian", count=3):
+    """48 x 48 texel windows around random visible texels of every cascade against the oracle's
+    Eq. 2 over every leaf that can reach the window."""
+    w = m["w"]
+    for k, cas in enumerate(cascades):
+        vis = vis_all[k]
         jj, ii = np.nonzero(vis)
-        for _ in range(3):  # 48 x 48 texel windows around random visible texels
+        for _ in range(count):
             a = rng.integers(len(jj))
             j0, i0 = max(jj[a] - 24, 0), max(ii[a] - 24, 0)
             wj, wi = np.nonzero(vis[j0:j0 + 48, i0:i0 + 48])
@@ -134,12 +142,45 @@ def test_discretize_full_frame_sampled(gpu, large):
             p = odisc.clamp_to_domain(odisc.texel_centres(cas, si, sj), m["dom"])
             box = (p[:, 0].min(), p[:, 1].min(), p[:, 0].max(), p[:, 1].max())
             sub = _reaching(m["leaves"], w.cutoff, box)
-            field = odisc.RBFField({key: m["leaves"][key][sub] for key in ("x", "y", "c", "v", "sigma")}, w.cutoff)
+            field = odisc.RBFField({key: m["leaves"][key][sub] for key in ("x", "y", "c", "v", "sigma")}, w.cutoff,
+                                   basis)
             ref, _ = field.evaluate(p)
             got = tex[k][sj, si]
             tol = G.texel_tolerance(m["leaves"], ref)
             err = np.abs(got - ref)
             assert np.all(err <= tol), f"cascade {k}: max error {err.max()} at {np.argmax(err - tol)}"
+
+
+def test_wendland_discretize_windows(gpu, large):
+    m = large
+    W = m["L"].with_basis("wendland")
+    api.pack_leaves(W)
+    tex = api.discretize(W, m["dom"], m["cas"]).cpu().numpy()
+    del W
+    for k in range(len(m["cs"])):
+        assert np.array_equal(np.isfinite(tex[k]), m["vis"][k])
+    _check_windows(m, m["cs"], m["vis"], tex, np.random.default_rng(2027), basis="wendland")
+
+
+def test_texel_reuse_next_frame_windows(gpu, large):
+    """The second frame of a flight, built by copying the first frame's blocks, against the oracle."""
+    m = large
+    w = m["w"]
+    c_min = float(m["leaves"]["c"].min())
+    cams = synth.camera_path(m["cam"], 2, step=2.0, yaw_step_deg=0.05)
+    cas0, cas1 = (api.fit_cascades(c, m["dom"], w.cascades, w.tex_n, w.split_lambda, w.overlap, c_min, aligned=True)
+                  for c in cams)
+    tex0 = api.discretize(m["L"], m["dom"], cas0)
+    reused = gpu.zeros(1, dtype=gpu.int32, device="cuda")
+    tex = api.discretize_reuse(m["L"], m["dom"], cas1, cas0, tex0, reused=reused).cpu().numpy()
+    del tex0
+    views = [api.CascadeView(c) for c in cas1]
+    vis = [odisc.visibility(v) for v in views]
+    for k in range(len(views)):
+        assert np.array_equal(np.isfinite(tex[k]), vis[k]), k
+    _say(f"{int(reused.item())} blocks copied")
+    assert int(reused.item()) > 0
+    _check_windows(m, views, vis, tex, np.random.default_rng(2028))
 
 
 @pytest.fixture(scope="module")
