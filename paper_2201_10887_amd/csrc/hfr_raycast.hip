@@ -390,7 +390,7 @@ __device__ int first_hit(const Ray& r, const RayCas& c, int k, const float* __re
 // outside the image.  G lanes (an aligned group, s = 0 .. G - 1) may share a
 // pixel (see first_hit); lane s = 0 writes its results.  Returns true when
 // the step budget ran out: nothing is written for the pixel then.
-template <bool BACKWARD, int G>
+template <bool BACKWARD, int G, bool NEARER = false>
 __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row, const float* __restrict__ tex,
                                               const float* __restrict__ mip, float* __restrict__ depth,
                                               int32_t* __restrict__ hit, const float* __restrict__ gdepth,
@@ -406,7 +406,7 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
         if (hf < 0 || ((hf >> 29) & 3) != S.tag) g = 0.0f;  // another surface is nearer, or none is hit
     }
     // the nearer pass sees only what lies in front of the surfaces drawn so far
-    const float clip = (!BACKWARD && S.nearer) ? depth[p] : INFINITY;
+    const float clip = (!BACKWARD && NEARER) ? depth[p] : INFINITY;
     // in the adjoint every lane stays to the end (the scatter uses wave-wide shuffles)
     const bool live = in_image && (!BACKWARD || (g != 0.0f && isfinite(g)));
     const double sx = ((col + 0.5) / A.W) * 2.0 - 1.0;
@@ -500,7 +500,7 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
     }
     if (!BACKWARD) {
         // a nearer pass replaces only what it finds in front (a blend may land a little behind)
-        if (!deferred && s == 0 && (!S.nearer || (found && (float)out_t < clip))) {
+        if (!deferred && s == 0 && (!NEARER || (found && (float)out_t < clip))) {
             depth[p] = (float)out_t;
             hit[p] = hid;
         }
@@ -566,14 +566,14 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
 // at most 80 VGPRs).  With a workspace (work[0] = queue length, work[1]
 // unused, work[2 ..] = pixel indices) a pixel whose walk exceeds RAY_BUDGET
 // steps is queued instead of finished.
-template <bool BACKWARD>
+template <bool BACKWARD, bool NEARER>
 __global__ __launch_bounds__(256, BACKWARD ? 4 : 6) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
                                                       const float* __restrict__ mip, float* __restrict__ depth,
                                                       int32_t* __restrict__ hit, const float* __restrict__ gdepth,
                                                       float* __restrict__ gtex, int* __restrict__ work, SurfaceArgs S)
 {
     const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
-    const bool deferred = raycast_pixel<BACKWARD, 1>(A, col, row, tex, mip, depth, hit, gdepth, gtex, 0,
+    const bool deferred = raycast_pixel<BACKWARD, 1, NEARER>(A, col, row, tex, mip, depth, hit, gdepth, gtex, 0,
                                                      work ? RAY_BUDGET : INT_MAX, S);
     if (!work) return;
     const uint64_t m = __ballot(deferred);  // one queue reservation per wave
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256, BACKWARD ? 4 : 6) void raycast_kernel(RayArgs 
 // loop condition is wave-uniform; a lane group whose entry lies past the
 // queue's end walks nothing but stays with its wave (the adjoint's scatter
 // uses wave-wide shuffles).
-template <bool BACKWARD>
+template <bool BACKWARD, bool NEARER>
 __global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const float* __restrict__ tex,
                                                            const float* __restrict__ mip, float* __restrict__ depth,
                                                            int32_t* __restrict__ hit, const float* __restrict__ gdepth,
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const floa
         const int idx = first + lane / G;
         const bool has = idx < count;
         const int p = has ? work[2 + idx] : 0;
-        raycast_pixel<BACKWARD, G>(A, has ? p % A.W : A.W, has ? p / A.W : 0, tex, mip, depth, hit, gdepth, gtex, s,
+        raycast_pixel<BACKWARD, G, NEARER>(A, has ? p % A.W : A.W, has ? p / A.W : 0, tex, mip, depth, hit, gdepth, gtex, s,
                                    INT_MAX, S);
     }
 }
@@ -709,12 +709,27 @@ void launch_raycast(const RayArgs& A, const float* tex, const float* mip, float*
 {
     if (work) zero_queue_kernel<<<1, 64, 0, s>>>(work);
     const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
-    raycast_kernel<BACKWARD><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
+    // the nearer pass is its own instantiation: the plain walk keeps no clip depth in registers
+    bool nearer = false;
+    if constexpr (!BACKWARD) nearer = S.nearer;
+    if constexpr (!BACKWARD) {
+        if (nearer)
+            raycast_kernel<false, true><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
+    }
+    if (!nearer)
+        raycast_kernel<BACKWARD, false><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
     if (!work) return;
     // persistent: enough lane groups that a typical queue is taken in one round
     const int64_t pixels = (int64_t)A.W * A.H;
     const int blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(64, pixels / 1024));
-    raycast_tail_kernel<BACKWARD><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
+    if constexpr (!BACKWARD) {
+        if (nearer)
+            raycast_tail_kernel<false, true><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex,
+                                                                               work, S);
+    }
+    if (!nearer)
+        raycast_tail_kernel<BACKWARD, false><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex,
+                                                                               work, S);
 }
 
 }  // namespace
