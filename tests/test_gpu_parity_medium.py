@@ -237,3 +237,52 @@ def test_backward_full_frame_sampled(gpu, medium, standin):
     for got, want in ((gv.cpu().numpy(), gv_ref), (gs.cpu().numpy(), gs_ref)):
         err, per = G.grad_close(got, want)
         assert err <= 1e-3 and per.mean() >= 0.999, (err, per.mean())
+
+
+def test_nearer_surface_composite_sampled(gpu, medium, standin):
+    """Two surfaces at full size: the terrain stand-in and a water stand-in above it on part of the
+    frame (the terrain plus a seeded smooth rise, below the domain top).  The GPU casts the terrain,
+    then the water's nearer pass; sampled pixels against the oracle's per-surface casts composited by
+    the nearer hit."""
+    from oracle import composite
+    m = medium
+    rng = np.random.default_rng(31)
+    phase = rng.uniform(0, 2 * np.pi, 4)
+    water = np.empty_like(standin)
+    for k, c in enumerate(m["cs"]):
+        x = c.x0 + np.arange(c.n) * c.hx
+        y = c.y0 + np.arange(c.n) * c.hy
+        X, Y = np.meshgrid(x / 3000.0, y / 3000.0)
+        rise = 6.0 * (np.sin(X + phase[0]) * np.cos(Y + phase[1]) + 0.5 * np.sin(2.3 * X + phase[2] + 1.7 * Y))
+        water[k] = np.minimum(standin[k] + rise, m["dom"].zmax - 1.0).astype(np.float32)
+        water[k][~np.isfinite(standin[k])] = -np.inf
+    water = water.astype(np.float32)
+    t0, t1 = gpu.as_tensor(standin, device="cuda"), gpu.as_tensor(water, device="cuda")
+    m0, m1 = api.build_maxmip(t0), api.build_maxmip(t1)
+    work = api.ray_workspace(m["cam"], "cuda")
+    depth, hit = api.raycast(m["cam"], m["dom"], m["cas"], t0, m0, work=work)
+    api.raycast_nearer(m["cam"], m["dom"], m["cas"], t1, m1, 1, depth, hit, work=work)
+    dg, hg = depth.cpu().numpy().ravel(), hit.cpu().numpy().ravel().astype(np.int64)
+    cam = m["cam"]
+    pix = rng.choice(cam.width * cam.height, 200_000, replace=False)
+    rays = [oray.raycast(cam, m["dom"], m["cs"], t, cols=pix % cam.width, rows=pix // cam.width, threads=16)
+            for t in (standin, water)]
+    comp = composite.nearest(rays)
+    assert (comp["surface"] == 1).mean() > 0.05 and (comp["surface"] == 0).mean() > 0.05
+    dg, hg = dg[pix], hg[pix]
+    sg = np.where(hg >= 0, hg >> composite.SURFACE_SHIFT, -1)
+    ext = m["dom"].extent
+    differ = np.nonzero(sg != comp["surface"])[0]
+    for p in differ:  # a different choice only where both surfaces are hit at (nearly) one depth
+        d0, d1 = rays[0]["depth"][p], rays[1]["depth"][p]
+        assert np.isfinite(d0) and np.isfinite(d1) and abs(d0 - d1) <= 1e-4 * ext, (p, d0, d1, sg[p])
+    assert len(differ) <= 1e-3 * len(pix)
+    tag_mask = (1 << composite.SURFACE_SHIFT) - 1
+    bad = 0
+    for s, tex in ((0, standin), (1, water)):
+        sel = np.nonzero((sg == s) & (comp["surface"] == s))[0]
+        ref = {key: rays[s][key][sel] for key in ("depth", "hit", "dirs")}
+        # every mismatch explained per surface; the rate over all sampled pixels of the frame
+        bad += G.compare_hits(dg[sel], hg[sel] & tag_mask, ref, cam, m["dom"], m["cs"], tex, allow_rate=None,
+                              what=f"medium surface {s}")[0]
+    assert bad <= 1e-5 * len(pix), bad
