@@ -396,6 +396,23 @@ hfr_status hfr_raycast_backward_surface(const hfr_camera* cam, const hfr_domain*
                                         const float* grad_depth, float* grad_tex, int32_t* work,
                                         hfr_stream stream);
 
+/* hfr_raycast for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * long-ray queue lives in a library-owned static device array instead of a
+ * caller workspace, and the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  Outputs are hfr_raycast's with a workspace.
+ * The array holds the queue of at most hfr_raycast_static_max_pixels() pixels
+ * (4,194,304: 16 MiB per device, held from the first call on that device until
+ * the process ends); a larger image returns HFR_EINVAL.  Every call on one
+ * device shares that device's array and clears its count first, so calls on
+ * one device that overlap in time (different streams, or threads without
+ * ordering) race and give wrong results: order them on one stream.  The
+ * stream must belong to the current device (else HFR_EINVAL); the first call
+ * on a device looks up the array's address (HFR_EDEVICE if that fails). */
+hfr_status hfr_raycast_static(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas, int32_t K,
+                              const float* tex, const float* mip, float* depth, int32_t* hit, hfr_stream stream);
+hfr_status hfr_raycast_static_max_pixels(int64_t* pixels);
+
 /* Adjoint of hfr_discretize (Eq. 2 and Eq. 1): ACCUMULATES into the
  * caller-zeroed grad_v and grad_sigma (device float[n])
  *   grad_v[j]     += g_s w_j / S0

@@ -105,6 +105,8 @@ SIGNATURES = {
     "hfr_neighbours_device_fill": ([PP(Leaves), F32, P, P, P], I32),
     "hfr_build_quadtree_device": ([P, I64, F64, F64, F64, I32, F64, P, P, PP(I64), P], I32),
     "hfr_quadtree_device_leaves": ([I64, F64, F64, F64, I32, P, P, I64, P, P, P, P, P, P, P, P], I32),
+    "hfr_raycast_static": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P], I32),
+    "hfr_raycast_static_max_pixels": ([PP(I64)], I32),
     "hfr_raycast_nearer": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, I32, P, P, P, P], I32),
     "hfr_raycast_backward_surface": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, I32, P, P, P, P, P], I32),
     "hfr_discretize_backward": ([PP(Leaves), PP(Domain), PP(Cascade), I32, P, P, P, P, P], I32),

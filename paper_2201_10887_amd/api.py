@@ -394,6 +394,24 @@ def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, st
     return depth, hit
 
 
+def raycast_static_max_pixels() -> int:
+    n = ctypes.c_int64()
+    call("hfr_raycast_static_max_pixels", ctypes.byref(n))
+    return n.value
+
+
+def raycast_static(cam, dom, cascades: ctypes.Array, tex, mip, depth, hit, stream=None):
+    """``raycast`` with the long-ray queue in the library's static device array (allocates nothing;
+    ``depth`` and ``hit`` are required)."""
+    import torch
+    K, N = len(cascades), cascades[0].n
+    call("hfr_raycast_static", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
+         _dev(depth, torch.float32, (cam.height, cam.width), "depth"),
+         _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _stream(stream))
+    return depth, hit
+
+
 def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, grad_tex=None, stream=None,
                      work=True):
     import torch

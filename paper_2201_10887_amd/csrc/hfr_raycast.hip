@@ -21,6 +21,7 @@
 // persistent kernel walks each queued ray with RAY_SPLIT lanes, which test
 // the next RAY_SPLIT nodes of the current level along the ray at once.
 #include <climits>
+#include <mutex>
 
 #include "hfr_device.h"
 
@@ -793,6 +794,79 @@ extern "C" hfr_status hfr_raycast_backward_surface(const hfr_camera* cam, const 
     launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work,
                          SurfaceArgs{surface, false, hit}, (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_backward_surface");
+    return hfr_ok();
+}
+
+// ------------------------------------------------------------------------
+// hfr_raycast_static: hfr_raycast with the long-ray queue in a library-owned
+// device array instead of a caller workspace, so the call allocates nothing.
+
+namespace {
+
+constexpr int64_t STATIC_QUEUE_PIXELS = int64_t(1) << 22;  // W x H at most (1920 x 1080, 2560 x 1600 fit)
+
+// The queue (count, unused word, pixel indices) of every hfr_raycast_static
+// call on a device: 16 MiB + 8 B, held by each device the library runs on
+// until the process ends.  Host code never names it directly: its device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) int32_t scratch[STATIC_QUEUE_PIXELS + 2];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+int32_t* scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (looked up on the first call).
+hfr_status scratch_address(hipStream_t stream, int32_t** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hfr_fail(HFR_EDEVICE, "raycast_static: hipGetDevice failed");
+    HFR_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "raycast_static: device %d beyond the %d supported", dev, MAX_DEVICES);
+    if (stream != nullptr) {
+        hipDevice_t sd = -1;
+        if (hipStreamGetDevice(stream, &sd) != hipSuccess)
+            return hfr_fail(HFR_EDEVICE, "raycast_static: hipStreamGetDevice failed");
+        HFR_REQUIRE(sd == dev, "raycast_static: the stream belongs to device %d, the current device is %d", (int)sd,
+                    dev);
+    }
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return hfr_fail(HFR_EDEVICE, "raycast_static: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        scratch_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return HFR_OK;
+}
+
+}  // namespace
+
+extern "C" hfr_status hfr_raycast_static_max_pixels(int64_t* pixels)
+{
+    HFR_REQUIRE(pixels != nullptr, "NULL output");
+    *pixels = STATIC_QUEUE_PIXELS;
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_raycast_static(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                                         int32_t K, const float* tex, const float* mip, float* depth, int32_t* hit,
+                                         hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
+    HFR_REQUIRE((int64_t)A.W * A.H <= STATIC_QUEUE_PIXELS,
+                "raycast_static: %d x %d pixels exceed the static queue's %lld (use hfr_raycast with a workspace)",
+                A.W, A.H, (long long)STATIC_QUEUE_PIXELS);
+    int32_t* work = nullptr;
+    st = scratch_address((hipStream_t)stream, &work);
+    if (st != HFR_OK) return st;
+    // the frame kernel appends to the queue after zero_queue_kernel has cleared its count
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr},
+                          (hipStream_t)stream);
+    HFR_LAUNCH_CHECK("raycast_static");
     return hfr_ok();
 }
 
