@@ -29,6 +29,7 @@ import math
 
 import numpy as np
 
+from . import discretize as _disc
 from .discretize import basis_dweight_dsigma, clamp_to_domain, texel_centres
 
 
@@ -78,3 +79,24 @@ def l2_loss(depth: np.ndarray, target: np.ndarray) -> tuple:
 
 def cutoff_weight(cutoff: float) -> float:
     return math.exp(-0.5 * cutoff * cutoff)
+
+
+def leaf_gradients_c(cascades, leaves: dict, cutoff: float, dom, gtex: np.ndarray, basis: str = "gaussian") -> tuple:
+    """``leaf_gradients`` by the plain-C form of Eq. 2's adjoint (``oracle/c/rbf_oracle.c``), for full-size
+    scenes: the same sums over every texel with a non-zero gradient and every leaf with w > 0."""
+    arrs = _disc._leaf_arrays(leaves)
+    n = len(arrs[0])
+    gv, gs = np.zeros(n), np.zeros(n)
+    lib = _disc._c_lib()
+    for k, cas in enumerate(cascades):
+        jj, ii = np.nonzero(gtex[k] != 0.0)
+        if len(jj) == 0:
+            continue
+        p = clamp_to_domain(texel_centres(cas, ii, jj), dom)
+        px, py = np.ascontiguousarray(p[:, 0]), np.ascontiguousarray(p[:, 1])
+        g = np.ascontiguousarray(gtex[k][jj, ii], np.float64)
+        rc = lib.oracle_rbf_adjoint(n, *(_disc._p(a) for a in arrs), float(cutoff), _disc.BASES.index(basis), len(p),
+                                    _disc._p(px), _disc._p(py), _disc._p(g), _disc._p(gv), _disc._p(gs))
+        if rc != 0:
+            raise ValueError("oracle_rbf_adjoint rejected its arguments")
+    return gv, gs

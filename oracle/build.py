@@ -5,7 +5,8 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = {"raycast_oracle": os.path.join(HERE, "c", "raycast_oracle.c")}
+SOURCES = {"raycast_oracle": os.path.join(HERE, "c", "raycast_oracle.c"),
+           "rbf_oracle": os.path.join(HERE, "c", "rbf_oracle.c")}
 
 
 def library_path(name: str) -> str:

@@ -31,10 +31,14 @@ clipping by rectangles.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
 
 import numpy as np
 from scipy.spatial import cKDTree
+
+from . import build as _build
 
 
 # ---------------------------------------------------------------- visibility
@@ -187,4 +191,62 @@ def discretize(cas, leaves: dict, dom, cutoff: float, field: RBFField = None, ba
     if field is None:
         field = RBFField(leaves, cutoff, basis)
     tex[jj, ii] = field.evaluate(p)[0]
+    return tex
+
+
+# ---------------------------------------------------------------- plain-C form for full-size scenes
+
+_clib = None
+
+
+def _c_lib():
+    global _clib
+    if _clib is None:
+        path = _build.library_path("rbf_oracle")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SOURCES["rbf_oracle"]):
+            _build.build(force=False)
+        lib = ctypes.CDLL(path)
+        P, I64, F64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        lib.oracle_rbf_eval.argtypes = [I64, P, P, P, P, P, F64, I32, I64, P, P, P, P, I32]
+        lib.oracle_rbf_eval.restype = I32
+        lib.oracle_rbf_adjoint.argtypes = [I64, P, P, P, P, P, F64, I32, I64, P, P, P, P, P]
+        lib.oracle_rbf_adjoint.restype = I32
+        _clib = lib
+    return _clib
+
+
+def _leaf_arrays(leaves: dict):
+    return [np.ascontiguousarray(leaves[k], np.float64) for k in ("x", "y", "c", "v", "sigma")]
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def rbf_evaluate_c(leaves: dict, cutoff: float, p: np.ndarray, basis: str = "gaussian", threads: int = 1) -> tuple:
+    """Eq. 2 at points ``p (m, 2)`` (already clamped) by the plain-C form in ``oracle/c/rbf_oracle.c``:
+    ``(value, sum_w)``, the same definition as ``RBFField.evaluate`` (every leaf with w > 0)."""
+    if basis not in BASES:
+        raise ValueError(f"unknown basis {basis!r}")
+    arrs = _leaf_arrays(leaves)
+    p = np.asarray(p, np.float64)
+    px, py = np.ascontiguousarray(p[:, 0]), np.ascontiguousarray(p[:, 1])
+    val, s0 = np.empty(len(p)), np.empty(len(p))
+    rc = _c_lib().oracle_rbf_eval(len(arrs[0]), *(_p(a) for a in arrs), float(cutoff), BASES.index(basis), len(p),
+                                  _p(px), _p(py), _p(val), _p(s0), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_rbf_eval rejected its arguments")
+    return val, s0
+
+
+def discretize_c(cas, leaves: dict, dom, cutoff: float, basis: str = "gaussian", threads: int = 1) -> np.ndarray:
+    """``discretize`` with Eq. 2 evaluated by the plain-C form (full-size scenes)."""
+    N = cas.n
+    vis = visibility(cas)
+    tex = np.full((N, N), -np.inf)
+    jj, ii = np.nonzero(vis)
+    if len(jj) == 0:
+        return tex
+    p = clamp_to_domain(texel_centres(cas, ii, jj), dom)
+    tex[jj, ii] = rbf_evaluate_c(leaves, cutoff, p, basis, threads)[0]
     return tex
