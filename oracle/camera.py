@@ -8,8 +8,9 @@ image plane spans ``tan(vfov/2)`` vertically and ``tan(vfov/2) * W / H``
 horizontally; pixel ``(col, row)`` is sampled at its centre with row 0 at the
 top; rays are unit length so the ray parameter is Euclidean distance.
 
-Pinned by ``tests/test_oracle_camera.py`` (orthonormal frame, centre pixel
-along forward for odd sizes, corner rays on the frustum edges).
+Pinned by ``tests/test_oracle_cascades.py::test_camera_frame_and_fov``
+(orthonormal frame, centre pixel along forward for odd sizes, corner rays on
+the frustum edges).
 """
 from __future__ import annotations
 

@@ -179,3 +179,29 @@ def test_aligned_fit_lattice(pos, yaw, pitch, N):
             os_ = base + math.floor((lo - base) / hs + 1e-9) * hs
             assert os_ + (N - 1) * hs < hi - 1e-9 * hs
             assert h < 2.0 ** 0.25 * (hi - lo) / (N - 2) + 1e-9
+
+
+@pytest.mark.parametrize("pos,yaw,pitch", CAMS)
+@pytest.mark.parametrize("N", [64, 256])
+def test_stable_fit_is_minimal(pos, yaw, pitch, N):
+    """Stable fit (Section 3: corners on the smallest-cell lattice, extents even multiples of it,
+    as much of the texture used as possible): the origin is the largest lattice point at or below
+    the polygon's box, and the extent the smallest even multiple of c_min reaching past it.  An
+    origin one c_min lower, or an extent 2 c_min wider, fails here."""
+    dom = synth.Domain(0.0, 0.0, 1024.0, 1024.0, 5.0, 300.0)
+    cam = _cam(pos, yaw, pitch, 256, 256)
+    c_min = 16.0
+    for c in cascades.fit_cascades(cam, dom, 3, N, 0.5, 0.05, c_min):
+        if not len(c.poly):
+            continue
+        for o, h, base, lo, hi in ((c.x0, c.hx, dom.x0, c.poly[:, 0].min(), c.poly[:, 0].max()),
+                                   (c.y0, c.hy, dom.y0, c.poly[:, 1].min(), c.poly[:, 1].max())):
+            tol = 1e-9 * c_min
+            m = (o - base) / c_min
+            assert abs(m - round(m)) < 1e-9
+            assert o <= lo + tol and o + c_min > lo + tol          # largest lattice point at or below lo
+            ext = h * (N - 1)
+            e = ext / (2 * c_min)
+            assert abs(e - round(e)) < 1e-9 and round(e) >= 1
+            assert o + ext >= hi - tol                              # reaches the box
+            assert round(e) == 1 or o + ext - 2 * c_min < hi - tol  # and no even multiple less does
