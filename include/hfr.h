@@ -38,11 +38,12 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 9
+#define HFR_ABI_VERSION 10
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
 #define HFR_MAX_SURFACES 4
+#define HFR_HIT_LIMIT (-2) /* hit word of a ray stopped by the walk's iteration cap */
 
 typedef int32_t hfr_status;
 enum {
@@ -110,6 +111,11 @@ typedef struct {
  *  cutoff            : truncation radius in units of sigma (the paper's 3.5)
  *  basis             : the weight function in Eq. 2 (HFR_BASIS_*); the packed
  *                      records hold the scale of the basis they were packed for
+ *  status            : device int32 or NULL, written by hfr_pack_leaves: HFR_OK,
+ *                      or HFR_EINVAL when some leaf has cutoff sigma <= sqrt(2)/2
+ *                      (Eq. 2's sum may then be empty where that leaf's cell is
+ *                      the only one near: its own reach no longer covers its
+ *                      square) or a non-finite value or width
  */
 #define HFR_BASIS_GAUSSIAN 0 /* Eq. 1: truncated Gaussian minus its value at the cutoff */
 /* Wendland's compactly supported C2 function (1 - u)^4 (4u + 1), u = r / (cutoff
@@ -132,6 +138,7 @@ typedef struct {
     float cutoff;
     double x0, y0, side;
     int32_t basis;
+    int32_t* status;
 } hfr_leaves;
 
 /* ------------------------------------------------------------------ misc */
@@ -283,8 +290,13 @@ hfr_status hfr_fit_cascades_aligned(const hfr_camera* cam, const hfr_domain* dom
 
 /* Writes L->packed (each record placed at its leaf's sorted position, found
  * through L->rank) and L->level_radius from x, y, v, c, sigma and cutoff
- * (call again whenever v, sigma or basis change).  EINVAL on NULL pointers,
- * n < 1, cutoff <= 0, max_depth outside [0, 15], an unknown basis. */
+ * (call again whenever v, sigma or basis change), and L->status when given:
+ * the leaves are refused there (HFR_EINVAL) when a width is too small for
+ * Eq. 2's sum to be non-empty everywhere (cutoff sigma <= sqrt(2)/2) or a
+ * value or width is not finite; the widths live on the device, so the
+ * verdict is a device word the caller reads once the stream has reached it.
+ * EINVAL (returned) on NULL pointers, n < 1, cutoff <= 0, max_depth outside
+ * [0, 15], an unknown basis. */
 hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream);
 
 /* Discretization (Section 4, Eq. 1 and Eq. 2, and the visibility texture of
@@ -326,8 +338,12 @@ hfr_status hfr_discretize_reuse(const hfr_leaves* L, const hfr_domain* dom, cons
  * by texture cell: the largest of the cell's four corner texels, -inf when
  * one is invisible, -inf on the last row and column; level l + 1 is the
  * 2x2 maximum of level l, down to 1 x 1.  mip: device float[K][(4N^2-1)/3],
- * levels finest first, each row-major.  EINVAL: N not a power of two in
- * [2, HFR_MAX_TEX_N], K outside [1, HFR_MAX_CASCADES]. */
+ * levels finest first, each row-major.  Level 0 is not stored: its N^2 slot
+ * at the start of each cascade's pyramid is left as the caller had it (the
+ * ray casts form those maxima from the four texels they load for the patch
+ * test); levels 1 .. log2 N are written.  tex: 16-byte aligned.  EINVAL: N
+ * not a power of two in [2, HFR_MAX_TEX_N], K outside [1, HFR_MAX_CASCADES],
+ * a misaligned tex. */
 hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, float* mip, hfr_stream stream);
 
 /* Ray casting (Section 5).  One ray per pixel, clipped to the domain's xy
@@ -341,9 +357,15 @@ hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, float* mip, 
  * depth: device float[H][W], +inf on a miss.  hit: device int32[H][W],
  * (s << 29) | (k << 26) | (j << 13) | i of hit A's cell (s: the surface
  * index, 0 here; see hfr_raycast_nearer), -1 on a miss.  Geometry is FP64
- * throughout.
+ * throughout.  A walk that reaches its iteration cap (8 N (log2 N + 2) + 64
+ * steps per cascade, more than a walk can need: each step descends a level
+ * or moves to a later cell) is reported, not taken for a miss: depth NaN and
+ * hit HFR_HIT_LIMIT.
  * work: device int32[W H + 2] scratch (its contents on entry do not matter;
- * the call overwrites them), or NULL.  With it, a ray still walking after a
+ * the call overwrites them), or NULL.  After the call work[0] holds the
+ * number of queued long rays and work[1] the number of rays stopped by the
+ * iteration cap (a status word the caller may read once the stream has
+ * reached it; 0 on a correct walk).  With it, a ray still walking after a
  * fixed number of cell steps is queued there and finished by a second
  * kernel in which several lanes share it, each walking one consecutive piece
  * of its parameter range (the first hit is that of the earliest piece with
@@ -374,8 +396,10 @@ hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom,
  * The visible point of a pixel is the nearest first hit over the surfaces.
  * Draw surface 0 with hfr_raycast, then every further surface s (1 ..
  * HFR_MAX_SURFACES - 1, its own textures and pyramids over the same
- * cascades) with hfr_raycast_nearer: each ray is clipped at the depth already
- * in depth[p], and a hit of surface s that lies in front replaces depth[p]
+ * cascades) with hfr_raycast_nearer: the search for each ray's first hit is
+ * clipped at the depth already in depth[p] (the partner hit of an overlap
+ * blend is searched unclipped: surface s's depth is its own, whatever lies
+ * behind), and a depth of surface s that lies in front replaces depth[p]
  * and hit[p] (tagged with s in bits 29-30); ties keep the earlier surface.
  * depth, hit: device in/out as written by the previous surfaces.  work: as
  * for hfr_raycast.  EINVAL: surface outside [1, HFR_MAX_SURFACES - 1], as

@@ -50,7 +50,7 @@ class Leaves(ctypes.Structure):
                 ("level_radius", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("order", ctypes.c_void_p),
                 ("max_depth", ctypes.c_int32),
                 ("cutoff", ctypes.c_float), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
-                ("side", ctypes.c_double), ("basis", ctypes.c_int32)]
+                ("side", ctypes.c_double), ("basis", ctypes.c_int32), ("status", ctypes.c_void_p)]
 
 
 class BatchField(ctypes.Structure):

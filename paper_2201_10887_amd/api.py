@@ -249,6 +249,7 @@ class DeviceLeaves:
         self.n = len(leaves["x"])
         self.packed = torch.empty((self.n, 4), dtype=torch.float32, device=device)
         self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.max_depth, self.cutoff = int(max_depth), float(cutoff)
         self.x0, self.y0, self.side = float(x0), float(y0), float(side)
         self.basis = BASIS_GAUSSIAN
@@ -270,6 +271,7 @@ class DeviceLeaves:
             raise ValueError("level index does not match max_depth")
         self.packed = torch.empty((self.n, 4), dtype=torch.float32, device=dev)
         self.level_radius = torch.zeros(max_depth + 1, dtype=torch.float32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.max_depth, self.cutoff = int(max_depth), float(cutoff)
         self.x0, self.y0, self.side = float(x0), float(y0), float(side)
         self.basis = BASIS_GAUSSIAN
@@ -286,6 +288,7 @@ class DeviceLeaves:
             raise ValueError("one value per leaf is required")
         other.packed = torch.empty_like(self.packed)
         other.level_radius = torch.zeros_like(self.level_radius)
+        other.status = torch.zeros_like(self.status)
         return other
 
     def with_basis(self, basis) -> "DeviceLeaves":
@@ -300,6 +303,7 @@ class DeviceLeaves:
         other.basis = b
         other.packed = torch.empty_like(self.packed)
         other.level_radius = torch.zeros_like(self.level_radius)
+        other.status = torch.zeros_like(self.status)
         return other
 
     def struct(self) -> Leaves:
@@ -308,14 +312,28 @@ class DeviceLeaves:
             _dev(getattr(self, name), torch.float32, None, name)
         _dev(self.rank, torch.int32, None, "rank")
         _dev(self.order, torch.int32, (self.n,), "order")
+        _dev(self.status, torch.int32, (1,), "status")
         return Leaves(self.n, self.x.data_ptr(), self.y.data_ptr(), self.c.data_ptr(), self.v.data_ptr(),
                       self.sigma.data_ptr(), self.packed.data_ptr(), self.level_radius.data_ptr(),
                       self.rank.data_ptr(), self.order.data_ptr(), self.max_depth, self.cutoff, self.x0, self.y0,
-                      self.side, self.basis)
+                      self.side, self.basis, self.status.data_ptr())
 
 
-def pack_leaves(L: DeviceLeaves, stream=None) -> None:
+def pack_leaves(L: DeviceLeaves, stream=None, check: bool = True) -> None:
+    """``hfr_pack_leaves``; with ``check`` the leaves' status word is read back (one synchronisation)
+    and a refusal raised as ``HfrError``."""
     call("hfr_pack_leaves", ctypes.byref(L.struct()), _stream(stream))
+    if check:
+        leaf_status(L)
+
+
+def leaf_status(L: DeviceLeaves) -> None:
+    """Raise ``HfrError`` (HFR_EINVAL) if the last ``pack_leaves`` refused the leaves (reads the device
+    status word: synchronises with its stream)."""
+    st = int(L.status.item())
+    if st != 0:
+        raise _lib.HfrError("hfr_pack_leaves", st, f"a leaf has cutoff * sigma <= sqrt(2)/2 (cutoff {L.cutoff}) "
+                                                    "or a non-finite value or width")
 
 
 def discretize(L: DeviceLeaves, dom, cascades: ctypes.Array, tex=None, mask=None, stream=None):

@@ -31,9 +31,10 @@ class Field:
         self.grad_v = torch.zeros(self.n, dtype=torch.float32, device=device) if with_grads else None
         self.grad_sigma = torch.zeros_like(self.grad_v) if with_grads else None
 
-    def refresh(self, stream=None):
-        """Re-derive the packed records after ``L.v`` or ``L.sigma`` changed."""
-        api.pack_leaves(self.L, stream)
+    def refresh(self, stream=None, check: bool = False):
+        """Re-derive the packed records after ``L.v`` or ``L.sigma`` changed (``check``: read back the
+        leaves' status word, one synchronisation)."""
+        api.pack_leaves(self.L, stream, check)
 
 
 @dataclasses.dataclass

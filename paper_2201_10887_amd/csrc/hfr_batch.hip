@@ -6,7 +6,7 @@
 // the work distribution:
 //  - discretize and its adjoint: one persistent launch over all 16 x 16
 //    texel blocks of all cascades of all views (per-XCD queues);
-//  - max-mipmap: one launch per five-level pass over all cascades;
+//  - max-mipmap: one launch over the 64 x 64-cell tiles of all cascades, one for their top levels;
 //  - ray casting and its adjoint: one persistent launch over all 64-pixel
 //    tiles of all views, taken wave by wave.
 // Every per-camera value (cascades, ray setup) lives in device memory, so
@@ -17,7 +17,7 @@
 
 #include "hfr_device.h"
 
-void maxmip_pass_shape(int N, int p, int* lin, int* nlev, int* tiles);
+void maxmip_pass_shape(int N, int p, int* tiles);
 
 namespace {
 
@@ -84,7 +84,7 @@ struct hfr_batch_plan {
     std::vector<int> cas_off;       // first cascade of each view in `cas`
     std::vector<hfr_cascade> cas;   // from the last hfr_batch_set_cameras
     std::vector<int> tex_start, mip_start, ray_start;
-    int pass_blocks[HFR_MIP_PASSES] = {0, 0, 0};
+    int pass_blocks[HFR_MIP_PASSES] = {};
     hfr_batch_tuning tuning{4, 4, 32, 8};
     bool cameras_set = false, backward_ok = false, upload_pending = false;
     // pinned staging of the per-camera descriptors
@@ -166,7 +166,7 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     }
     bool bwd = true;
     int64_t tex_blocks = 0, n_tex = 0;
-    int64_t pass_total[HFR_MIP_PASSES] = {0, 0, 0};
+    int64_t pass_total[HFR_MIP_PASSES] = {};
     for (int v = 0; v < n_views; ++v) {
         const hfr_batch_view& V = views[v];
         HFR_REQUIRE(V.field >= 0 && V.field < n_fields, "view %d names field %d of %d", v, V.field, n_fields);
@@ -176,6 +176,7 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
         HFR_REQUIRE(V.width >= 1 && V.width <= 16384 && V.height >= 1 && V.height <= 16384,
                     "view %d: image size %dx%d outside [1, 16384]", v, V.width, V.height);
         HFR_REQUIRE(V.tex && V.mip && V.depth && V.hit, "view %d: NULL texture, pyramid or image buffer", v);
+        HFR_REQUIRE(reinterpret_cast<uintptr_t>(V.tex) % 16 == 0, "view %d: textures must be 16-byte aligned", v);
         HFR_REQUIRE(V.split_lambda >= 0 && V.split_lambda <= 1 && V.overlap >= 0 && V.c_min > 0 &&
                         std::isfinite(V.overlap) && std::isfinite(V.c_min),
                     "view %d: invalid split_lambda, overlap or c_min", v);
@@ -184,8 +185,8 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
         tex_blocks += V.K * gx * gx;
         n_tex += V.K;
         for (int p = 0; p < HFR_MIP_PASSES; ++p) {
-            int lin, nlev, tiles;
-            maxmip_pass_shape(V.N, p, &lin, &nlev, &tiles);
+            int tiles;
+            maxmip_pass_shape(V.N, p, &tiles);
             pass_total[p] += (int64_t)V.K * tiles * tiles;
         }
     }
@@ -235,8 +236,8 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
             it.gtex = V.grad_tex ? V.grad_tex + k * NN : nullptr;
             q->tex_start[t + 1] = q->tex_start[t] + gx * gx;
             for (int p = 0; p < HFR_MIP_PASSES; ++p) {
-                int lin, nlev, tiles;
-                maxmip_pass_shape(V.N, p, &lin, &nlev, &tiles);
+                int tiles;
+                maxmip_pass_shape(V.N, p, &tiles);
                 int* ms = &q->mip_start[p * (n_tex + 1)];
                 ms[t + 1] = ms[t] + tiles * tiles;
             }

@@ -188,7 +188,7 @@ struct BatchView {
 
 constexpr int HFR_QUEUE_DISC = 0, HFR_QUEUE_RAY = 8, HFR_QUEUE_RAY_BWD = 16, HFR_QUEUE_DISC_BWD = 24;
 constexpr int HFR_QUEUE_WORDS = 32;
-constexpr int HFR_MIP_PASSES = 3;  // ceil(log2(HFR_MAX_TEX_N) / 5)
+constexpr int HFR_MIP_PASSES = 2;  // 64 x 64-cell tiles to level 6, then one workgroup per cascade to the top
 
 struct BatchDev {
     const BatchField* fields;

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restric
                                                           const int32_t* __restrict__ rank, double x0, double y0,
                                                           float cutoff, float scale, float side, int max_depth,
                                                           float4* __restrict__ out, float* __restrict__ radius,
-                                                          int64_t n)
+                                                          int* __restrict__ status, int64_t n)
 {
     __shared__ int level_max[16];  // max_depth <= 15; positive floats order as ints, 0 = no leaf seen
     if (threadIdx.x < 16) level_max[threadIdx.x] = 0;
@@ -81,16 +81,20 @@ __global__ __launch_bounds__(256) void pack_leaves_kernel(const float* __restric
         if (p >= 0 && p < n) out[p] = make_float4(xa, ya, v[a], scale / sc);
         const float R = cutoff * sc * 1.00001f;
         atomicMax(&level_max[l], __float_as_int(R));
+        // Eq. 2 needs each leaf's own reach to cover its square (half-diagonal sqrt(2)/2 c)
+        if (status != nullptr && !(cutoff * sigma[a] > 0.70710678118654752f && isfinite(v[a]) && isfinite(sigma[a])))
+            *status = HFR_EINVAL;
     }
     __syncthreads();
     if (threadIdx.x <= (unsigned)max_depth && level_max[threadIdx.x] != 0)
         atomicMax(reinterpret_cast<int*>(radius) + threadIdx.x, level_max[threadIdx.x]);
 }
 
-__global__ void zero_floats_kernel(float* __restrict__ p, int n)
+__global__ void zero_floats_kernel(float* __restrict__ p, int n, int* __restrict__ status)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a < n) p[a] = 0.0f;
+    if (a == 0 && status != nullptr) *status = HFR_OK;
 }
 
 __device__ inline double clampd(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
@@ -759,12 +763,12 @@ extern "C" hfr_status hfr_pack_leaves(const hfr_leaves* L, hfr_stream stream)
     // record scale: exp2(-(s r)^2) is Eq. 1's Gaussian; for Wendland s r is r over the support radius
     const float scale = L->basis == HFR_BASIS_GAUSSIAN ? std::sqrt(HALF_LOG2E) : 1.0f / L->cutoff;
     hipStream_t s = (hipStream_t)stream;
-    zero_floats_kernel<<<1, 64, 0, s>>>(L->level_radius, L->max_depth + 1);
+    zero_floats_kernel<<<1, 64, 0, s>>>(L->level_radius, L->max_depth + 1, L->status);
     HFR_LAUNCH_CHECK("pack_leaves (radius reset)");
     const int64_t blocks = std::min<int64_t>((L->n + 255) / 256, 2048);
     pack_leaves_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
         L->x, L->y, L->v, L->c, L->sigma, L->rank, L->x0, L->y0, L->cutoff, scale, (float)L->side, L->max_depth,
-        reinterpret_cast<float4*>(L->packed), L->level_radius, L->n);
+        reinterpret_cast<float4*>(L->packed), L->level_radius, L->status, L->n);
     HFR_LAUNCH_CHECK("pack_leaves");
     return hfr_ok();
 }

@@ -35,6 +35,7 @@ struct SurfaceArgs {
     int tag;                       // surface index, written into bits 29-30 of every hit
     bool nearer;                   // forward: clip each ray at depth[p], write only a nearer hit
     const int32_t* __restrict__ filter;  // adjoint: only pixels whose hit carries this tag (NULL: all)
+    int* limit_count;              // rays stopped by the walk's iteration cap are counted here (NULL: not counted)
 };
 
 struct Ray {
@@ -212,7 +213,11 @@ __device__ inline float cell_texels(const float* __restrict__ tex, int N, int ci
 }
 
 // First root of the ray in [ta, tb] of cascade k: 1 with the hit in h, 0 when
-// there is none, -1 when the step budget runs out first.  G > 1: the G lanes
+// there is none, -1 when the step budget runs out first, -2 when the walk
+// reaches its iteration cap (every iteration descends a level or moves to a
+// later piece, so a walk never needs that many; the cap only guards against
+// a fault in that reasoning, and the caller reports the ray instead of
+// treating it as a miss).  G > 1: the G lanes
 // of an aligned group hold the same ray and call this together, and every
 // step tests the next G nodes of the current level along the ray at once
 // (lane s the s-th: entered after the s-th crossing of the merged x- and
@@ -383,7 +388,7 @@ __device__ int first_hit(const Ray& r, const RayCas& c, int k, const float* __re
             if (diff) l = min(31 - __clz(diff), l + (close ? 0 : 1));
         }
     }
-    return 0;
+    return -2;
 }
 
 // Pixel (col, row) of one view.  In the adjoint every lane of the wave must
@@ -431,13 +436,17 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
     if (r.d[2] > 0.0) tout = fmin(tout, (A.zmax - r.o[2]) / r.d[2]);
     else if (r.d[2] < 0.0) tin = fmax(tin, (A.zmax - r.o[2]) / r.d[2]);
     else if (r.o[2] > A.zmax) tin = INFINITY;
+    // the nearer pass clips the search for the first hit only: the second hit of an overlap
+    // blend is this surface's own, wherever the surfaces drawn so far lie (the adjoint, which
+    // walks unclipped, finds the same pair)
+    const double tfull = tout;
     tout = fmin(tout, (double)clip);
 
     double out_t = INFINITY, cA = 0.0, cB = 0.0;
     int hid = -1;
     Hit HA, HB;
     HB.k = -1;
-    bool found = false, deferred = false;
+    bool found = false, deferred = false, limited = false;
     const double dd = r.d[0] * A.c[0].vx + r.d[1] * A.c[0].vy;
     const bool fwd = dd >= 0.0;
     // Cascades in the order the ray's offset sweeps them: increasing k when the offset
@@ -460,7 +469,8 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
             if (sa == 0) continue;
             found = true;
             if (sa < 0) {
-                deferred = true;
+                deferred = sa == -1;
+                limited = sa == -2;
                 continue;
             }
             hid = (S.tag << 29) | (HA.k << 26) | (HA.j << 13) | HA.i;
@@ -473,11 +483,13 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
                 const double dA = offset_at(r, ck, HA.t);
                 if (up ? dA >= lo : dA <= hi) {
                     double tb0, tb1;
-                    segment(r, A.c[pk], lo, hi, tin, tout, tb0, tb1);
+                    segment(r, A.c[pk], lo, hi, tin, tfull, tb0, tb1);
                     const int sb = first_hit<G>(r, A.c[pk], pk, tex + pk * NN, mip + pk * MM, tb0, tb1, HB,
                                                       budget, s);
-                    if (sb < 0) {
+                    if (sb == -1) {
                         deferred = true;
+                    } else if (sb == -2) {
+                        limited = true;
                     } else if (sb > 0) {
                         const double delta = hi - lo;
                         double al = (dA - lo) / delta, dal = dd / delta;
@@ -499,14 +511,20 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
             }
         }
     }
+    if (limited && !deferred && s == 0 && S.limit_count != nullptr) atomicAdd(S.limit_count, 1);
     if (!BACKWARD) {
-        // a nearer pass replaces only what it finds in front (a blend may land a little behind)
-        if (!deferred && s == 0 && (!NEARER || (found && (float)out_t < clip))) {
+        // a nearer pass replaces only what it finds in front (a blend may land a little behind);
+        // a ray stopped by the iteration cap is reported (NaN, HFR_HIT_LIMIT), never taken for a miss
+        if (!deferred && s == 0 && limited) {
+            depth[p] = NAN;
+            hit[p] = -2;
+        } else if (!deferred && s == 0 && (!NEARER || (found && (float)out_t < clip))) {
             depth[p] = (float)out_t;
             hit[p] = hid;
         }
         return deferred;
     }
+    found = found && !limited;
     // gradient scatter: wave-combined for lanes that share a cell (common near
     // the camera, where many pixels land in one texture cell), direct atomics
     // for the rest
@@ -564,8 +582,8 @@ __device__ __forceinline__ bool raycast_pixel(const RayArgs& A, int col, int row
 }
 
 // Frame kernel: one lane per pixel (6 waves per SIMD for the forward pass:
-// at most 80 VGPRs).  With a workspace (work[0] = queue length, work[1]
-// unused, work[2 ..] = pixel indices) a pixel whose walk exceeds RAY_BUDGET
+// at most 80 VGPRs).  With a workspace (work[0] = queue length, work[1] =
+// rays stopped by the iteration cap, work[2 ..] = pixel indices) a pixel whose walk exceeds RAY_BUDGET
 // steps is queued instead of finished.
 template <bool BACKWARD, bool NEARER>
 __global__ __launch_bounds__(256, BACKWARD ? 4 : 6) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
@@ -616,7 +634,7 @@ __global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const floa
 
 __global__ void zero_queue_kernel(int* __restrict__ work)
 {
-    if (threadIdx.x == 0) work[0] = 0;
+    if (threadIdx.x < 2) work[threadIdx.x] = 0;  // queue length, rays stopped by the iteration cap
 }
 
 // Persistent form over every view of a batch: each wave takes runs of
@@ -652,7 +670,7 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
             const int local = w - v_lo;
             const int tx = local % V.tiles_x, ty = local / V.tiles_x;
             raycast_pixel<BACKWARD, 1>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,
-                                       V.gdepth, V.gtex, 0, INT_MAX, SurfaceArgs{0, false, nullptr});
+                                       V.gdepth, V.gtex, 0, INT_MAX, SurfaceArgs{0, false, nullptr, nullptr});
         }
     }
 }
@@ -706,8 +724,10 @@ namespace {
 // The frame kernel, then (with a workspace) the queue of long rays.
 template <bool BACKWARD>
 void launch_raycast(const RayArgs& A, const float* tex, const float* mip, float* depth, int32_t* hit,
-                    const float* gdepth, float* gtex, int32_t* work, const SurfaceArgs& S, hipStream_t s)
+                    const float* gdepth, float* gtex, int32_t* work, const SurfaceArgs& S0, hipStream_t s)
 {
+    SurfaceArgs S = S0;
+    S.limit_count = work ? work + 1 : nullptr;
     if (work) zero_queue_kernel<<<1, 64, 0, s>>>(work);
     const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
     // the nearer pass is its own instantiation: the plain walk keeps no clip depth in registers
@@ -743,7 +763,7 @@ extern "C" hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, 
     hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
-    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr},
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr, nullptr},
                           (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast");
     return hfr_ok();
@@ -759,7 +779,7 @@ extern "C" hfr_status hfr_raycast_nearer(const hfr_camera* cam, const hfr_domain
     HFR_REQUIRE(tex && mip && depth && hit, "NULL texture, mipmap or output");
     HFR_REQUIRE(surface >= 1 && surface <= HFR_MAX_SURFACES - 1, "surface %d outside [1, %d]", surface,
                 HFR_MAX_SURFACES - 1);
-    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{surface, true, nullptr},
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{surface, true, nullptr, nullptr},
                           (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_nearer");
     return hfr_ok();
@@ -773,7 +793,7 @@ extern "C" hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_doma
     hfr_status st = ray_args(cam, dom, cas, K, &A);
     if (st != HFR_OK) return st;
     HFR_REQUIRE(tex && mip && grad_depth && grad_tex, "NULL texture, mipmap or gradient");
-    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work, SurfaceArgs{0, false, nullptr},
+    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work, SurfaceArgs{0, false, nullptr, nullptr},
                          (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_backward");
     return hfr_ok();
@@ -792,7 +812,7 @@ extern "C" hfr_status hfr_raycast_backward_surface(const hfr_camera* cam, const 
     HFR_REQUIRE(surface >= 0 && surface <= HFR_MAX_SURFACES - 1, "surface %d outside [0, %d]", surface,
                 HFR_MAX_SURFACES - 1);
     launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work,
-                         SurfaceArgs{surface, false, hit}, (hipStream_t)stream);
+                         SurfaceArgs{surface, false, hit, nullptr}, (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_backward_surface");
     return hfr_ok();
 }
@@ -864,7 +884,7 @@ extern "C" hfr_status hfr_raycast_static(const hfr_camera* cam, const hfr_domain
     st = scratch_address((hipStream_t)stream, &work);
     if (st != HFR_OK) return st;
     // the frame kernel appends to the queue after zero_queue_kernel has cleared its count
-    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr},
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr, nullptr},
                           (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast_static");
     return hfr_ok();

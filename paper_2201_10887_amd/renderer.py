@@ -73,6 +73,9 @@ class Renderer:
         # measurable, so off unless asked for)
         self.count_reused = False
         self.reused_blocks = torch.zeros(1, dtype=torch.int32, device=device)
+        # bumped by every call that rewrites textures or leaf records: an autograd node checks that
+        # what its backward reads is still its own frame's
+        self.generation = 0
 
     def ray_work(self, cam, backward: bool = False):
         """The long-ray queue for this camera's image size (None when disabled)."""
@@ -89,6 +92,7 @@ class Renderer:
         time; when the frame is throughput-bound, walking them after the rest costs more than it
         saves.  Returns the median times (ms)."""
         import torch
+        self.generation += 1
         cas = self.fit(cam)
         api.discretize(self.L, self.dom, cas, self.tex, self.mask)
         api.build_maxmip(self.tex, self.mip)
@@ -141,12 +145,14 @@ class Renderer:
         self._prev_cas = None
         self._spare = [torch.empty_like(tex) for _, tex, _, _ in self.surfaces()] if on else []
 
-    def refresh_leaves(self, stream=None):
-        """Re-derive the packed leaf records after ``L.v`` or ``L.sigma`` changed."""
+    def refresh_leaves(self, stream=None, check: bool = False):
+        """Re-derive the packed leaf records after ``L.v`` or ``L.sigma`` changed (``check``: read back
+        the leaves' status word and raise if a width is too small for Eq. 2; one synchronisation)."""
         self._prev_cas = None
-        api.pack_leaves(self.L, stream)
+        self.generation += 1
+        api.pack_leaves(self.L, stream, check)
         for surf in self.extra:
-            api.pack_leaves(surf["L"], stream)
+            api.pack_leaves(surf["L"], stream, check)
 
     def add_surface(self, v) -> int:
         """A further heightfield on the same cells, e.g. terrain plus relative water depth (Section 2):
@@ -156,6 +162,7 @@ class Renderer:
         s = 1 + len(self.extra)
         if s >= 4:
             raise ValueError("at most four surfaces")
+        self.generation += 1
         L = self.L.with_values(v)
         api.pack_leaves(L)
         d = self.dom
@@ -176,6 +183,7 @@ class Renderer:
             yield surf["L"], surf["tex"], surf["mask"], surf["mip"]
 
     def forward(self, cam, cascades=None, depth=None, hit=None, stream=None):
+        self.generation += 1
         cas = self.fit(cam) if cascades is None else cascades
         for s, (L, tex, mask, mip) in enumerate(self.surfaces()):
             if self.texel_reuse and self._prev_cas is not None:
@@ -199,19 +207,25 @@ class Renderer:
             api.raycast_nearer(cam, self.dom, cas, surf["tex"], surf["mip"], s, depth, hit, stream, work)
         return depth, hit, cas
 
-    def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None, hit=None):
+    def backward(self, cam, cascades, grad_depth, grad_tex, grad_v, grad_sigma, stream=None, hit=None,
+                 surfaces=None):
         """Accumulates into the (caller-zeroed) gradient buffers.  With several surfaces, ``hit`` (the
         forward pass's) routes each pixel's gradient to the surface it shows: surface 0 into grad_tex and
         grad_v, surface s into its own zeroed ``extra[s - 1]["grad_tex"]`` / ``["grad_v"]``; the widths
-        are shared, so grad_sigma sums over the surfaces."""
+        are shared, so grad_sigma sums over the surfaces.  ``surfaces``: (textures, pyramids) per surface
+        to differentiate instead of the renderer's current ones (a kept copy of an earlier frame)."""
         work = self.ray_work(cam, backward=True)
+        views = [(L, tex, mip) for L, tex, _, mip in self.surfaces()]
+        if surfaces is not None:
+            views = [(L, t, m) for (L, _, _), (t, m) in zip(views, surfaces)]
         if not self.extra:
-            api.raycast_backward(cam, self.dom, cascades, self.tex, self.mip, grad_depth, grad_tex, stream, work)
-            api.discretize_backward(self.L, self.dom, cascades, self.tex, grad_tex, grad_v, grad_sigma, stream)
+            L, tex, mip = views[0]
+            api.raycast_backward(cam, self.dom, cascades, tex, mip, grad_depth, grad_tex, stream, work)
+            api.discretize_backward(L, self.dom, cascades, tex, grad_tex, grad_v, grad_sigma, stream)
             return grad_v, grad_sigma
         if hit is None:
             raise ValueError("several surfaces: pass the forward pass's hit buffer")
-        for s, (L, tex, _, mip) in enumerate(self.surfaces()):
+        for s, (L, tex, mip) in enumerate(views):
             gt = grad_tex if s == 0 else self.extra[s - 1]["grad_tex"]
             gv = grad_v if s == 0 else self.extra[s - 1]["grad_v"]
             if s > 0:
@@ -231,28 +245,64 @@ def _make_function():
     import torch
 
     class RenderDepth(torch.autograd.Function):
-        """depth = render(v, sigma); backward gives d loss / d v and d loss / d sigma."""
+        """depth = render(v, sigma, *water_values); backward gives d loss / d v, d loss / d sigma and,
+        per further surface, d loss / d its values.
+
+        The adjoints read the frame's textures, pyramids and leaf records.  By default they are the
+        renderer's own buffers, so backward must come before the renderer draws again (it raises
+        otherwise, instead of differentiating another frame).  ``snapshot=True`` keeps copies of this
+        frame's textures, pyramids, values and widths, so several renders (e.g. two cameras) can be
+        summed into one loss."""
 
         @staticmethod
-        def forward(ctx, v, sigma, renderer: Renderer, cam):
+        def forward(ctx, v, sigma, renderer: Renderer, cam, snapshot: bool, *extra_v):
+            if len(extra_v) != len(renderer.extra):
+                raise ValueError(f"the renderer has {len(renderer.extra)} further surfaces: pass one value "
+                                 "tensor for each")
             L = renderer.L
             L.v.copy_(v.detach())
             L.sigma.copy_(sigma.detach())
+            for surf, ev in zip(renderer.extra, extra_v):
+                surf["L"].v.copy_(ev.detach())
             renderer.refresh_leaves()
             depth, hit, cas = renderer.forward(cam)
             ctx.renderer, ctx.cam, ctx.cas = renderer, cam, cas
-            ctx.mark_non_differentiable(hit)
-            return depth.clone(), hit.clone()
+            ctx.generation = renderer.generation
+            ctx.snapshot = None
+            if snapshot:
+                ctx.snapshot = {"v": v.detach().clone(), "sigma": sigma.detach().clone(),
+                                "extra_v": [e.detach().clone() for e in extra_v],
+                                "surfaces": [(tex.clone(), mip.clone()) for _, tex, _, mip in renderer.surfaces()]}
+            hit_out = hit.clone()
+            ctx.hit = hit_out if renderer.extra else None
+            ctx.mark_non_differentiable(hit_out)
+            return depth.clone(), hit_out
 
         @staticmethod
         def backward(ctx, grad_depth, grad_hit):
             r = ctx.renderer
+            surfaces = None
+            if ctx.snapshot is not None:
+                snap = ctx.snapshot
+                if r.generation != ctx.generation:  # another frame was drawn since: restore this one's leaves
+                    r.L.v.copy_(snap["v"])
+                    r.L.sigma.copy_(snap["sigma"])
+                    for surf, ev in zip(r.extra, snap["extra_v"]):
+                        surf["L"].v.copy_(ev)
+                    r.refresh_leaves()
+                surfaces = snap["surfaces"]
+            elif r.generation != ctx.generation:
+                raise RuntimeError("render_depth: the renderer drew another frame (or changed its leaves) before "
+                                   "this frame's backward; render with snapshot=True to sum several renders "
+                                   "into one loss")
             gd = torch.where(torch.isfinite(grad_depth), grad_depth, torch.zeros_like(grad_depth)).contiguous()
             gtex = torch.zeros_like(r.tex)
             gv = torch.zeros(r.L.n, dtype=torch.float32, device=r.tex.device)
             gs = torch.zeros_like(gv)
-            r.backward(ctx.cam, ctx.cas, gd, gtex, gv, gs)
-            return gv, gs, None, None
+            r.backward(ctx.cam, ctx.cas, gd, gtex, gv, gs, hit=ctx.hit, surfaces=surfaces)
+            # each backward leaves its own frame's leaf records behind it
+            extra_g = [surf["grad_v"].clone() for surf in r.extra]
+            return (gv, gs, None, None, None, *extra_g)
 
     return RenderDepth
 
@@ -260,9 +310,12 @@ def _make_function():
 _RenderDepth = None
 
 
-def render_depth(v, sigma, renderer: Renderer, cam):
-    """Differentiable depth image (and non-differentiable hit ids) of leaf values ``v`` and widths ``sigma``."""
+def render_depth(v, sigma, renderer: Renderer, cam, *extra_values, snapshot: bool = False):
+    """Differentiable depth image (and non-differentiable hit ids) of leaf values ``v`` and widths
+    ``sigma`` and, for a renderer with further surfaces, their values (one tensor per surface, each
+    differentiable too).  ``snapshot``: keep this frame's textures so that the renderer may draw other
+    frames before this one's backward."""
     global _RenderDepth
     if _RenderDepth is None:
         _RenderDepth = _make_function()
-    return _RenderDepth.apply(v, sigma, renderer, cam)
+    return _RenderDepth.apply(v, sigma, renderer, cam, bool(snapshot), *extra_values)
