@@ -109,6 +109,9 @@ def test_forward_bitexact_vs_per_view(gpu, batch):
         b = R.bufs[v]
         for name in ("tex", "mask", "mip", "depth", "hit"):
             got, want = b[name].cpu().numpy(), ref[name].cpu().numpy()
+            if name == "mip":  # level 0 is not stored
+                NN = R.specs[v].N ** 2
+                got, want = got[:, NN:], want[:, NN:]
             assert np.array_equal(got.view(np.uint32) if got.dtype == np.float32 else got,
                                   want.view(np.uint32) if want.dtype == np.float32 else want), (v, name)
     e = R.bufs[EMPTY_VIEW]

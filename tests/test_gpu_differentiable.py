@@ -19,6 +19,7 @@ import os
 import numpy as np
 import pytest
 
+from oracle import adjoint
 from paper_2201_10887_amd import api
 from tests import differentiable as D
 from tests import gpu_common as G
@@ -74,18 +75,49 @@ def test_autograd_equals_adjoint_entry_points(gpu, problem, gpu_grads):
         assert err <= 1e-5 and per.all(), err
 
 
-def test_loss_gradient_matches_oracle(problem, gpu_grads):
-    """Each side differentiates its own forward pass (textures equal within the texel
-    tolerance, depths within the depth tolerance), so the loss gradient per pixel differs
-    by up to twice the depth difference: the norm-relative bound holds, and every leaf's
-    difference is bounded by 1e-3 of the largest gradient (a leaf whose own gradient is
-    small can differ by more than 1e-3 of itself)."""
-    assert abs(gpu_grads["loss"] - problem["loss0"]) <= 1e-3 * problem["loss0"]
-    for got, want in ((gpu_grads["gv"], problem["gv"]), (gpu_grads["gs"], problem["gs"])):
-        err, _ = G.grad_close(got, want)
-        assert err <= 1e-3, err
+def test_loss_gradient_matches_oracle(gpu, problem, gpu_grads):
+    """Each side differentiates its own forward pass (textures equal within the texel tolerance,
+    depths within the depth tolerance).  At a near-grazing hit dt/dh = phi / f'(t) is ill
+    conditioned: a texel difference of an ulp moves a small leaf gradient by more than 1e-3 of
+    itself (over all pixels: norm 1.4e-4, the per-leaf rule on 98.6 % (v) and 98.3 % (sigma) of
+    the leaves).  Those are the rays the hit-cell rule exempts, so the loss here takes the pixels
+    both sides hit in the same cell at 2 degrees or more to the oracle's patch (all but 0.06 %).
+    What is left is each side's own depth in the loss gradient 2 (t - target): the two depths
+    differ by the texels' rounding, and that difference reaches every leaf under the pixel as an
+    absolute error of up to about 5e-5 of the largest leaf gradient (measured 5.3e-5), more than
+    1e-3 of a leaf whose gradient is a few percent of the largest.  The bound: norm within 1e-3,
+    every leaf within 2e-4 of the largest gradient, and the per-leaf rule (1e-3 of the leaf's own
+    value, or 1e-6 of the largest) on 99.5 % of the 2059 leaves (measured 99.90 % for v, 99.76 %
+    for sigma; one leaf is 0.05 %).  Given the same textures and depth gradient the two adjoints
+    agree on every leaf (test_gpu_gradients_full)."""
+    from paper_2201_10887_amd.renderer import Renderer, render_depth
+    s, base = problem["s"], problem["base"]
+    w = s.work
+    R = gpu_grads["R"]
+    v = gpu.tensor(s.leaves["v"], device="cuda", requires_grad=True)
+    sigma = gpu.tensor(s.leaves["sigma"], device="cuda", requires_grad=True)
+    target = problem["target"]
+    depth, hit = render_depth(v, sigma, R, s.cam)
+    keep = ((hit.detach().cpu().numpy().ravel() == base["hit"]) & np.isfinite(base["depth"]) & np.isfinite(target)
+            & G.well_conditioned(base, s.cascades, s.tex64))
+    print(f"tiny end to end: loss over {int(keep.sum())} of {int((np.isfinite(base['depth']) & np.isfinite(target)).sum())} "
+          f"pixels", flush=True)
+    m = gpu.as_tensor(keep.reshape(SIZE, SIZE), device="cuda")
+    tt = gpu.as_tensor(np.where(keep, target, 0.0).reshape(SIZE, SIZE).astype(np.float32), device="cuda")
+    diff = gpu.where(m, depth - tt, gpu.zeros_like(depth))
+    (diff * diff).sum().backward()
+    _, gd = adjoint.l2_loss(np.where(keep, base["depth"], np.inf), target)
+    gtex = adjoint.texel_gradients(base, gd, len(s.cascades), w.tex_n)
+    gv_ref, gs_ref = adjoint.leaf_gradients(s.cascades, s.field, s.dom, gtex)
+    for name, got, want in (("v", v.grad, gv_ref), ("sigma", sigma.grad, gs_ref)):
+        got = got.detach().cpu().numpy().astype(np.float64)
+        err, per = G.grad_close(got, want)
         worst = np.abs(got - want).max() / np.abs(want).max()
-        assert worst <= 1e-3, worst
+        print(f"tiny end to end d/d{name}: norm rel {err:.2e}, per-leaf rule on {per.mean():.5f}, worst {worst:.2e}",
+              flush=True)
+        assert err <= 1e-3, err
+        assert worst <= 2e-4, worst
+        assert per.mean() >= 0.995, per.mean()
 
 
 @pytest.mark.parametrize("which", ["v", "sigma"])
@@ -100,3 +132,32 @@ def test_gradient_matches_finite_differences(gpu_grads, which):
     assert len(leaf) == 64
     assert np.median(rel) <= 1e-3, (np.median(rel), rel.max())
     assert np.mean(rel <= 1e-2) >= 0.95, np.sort(rel)[-5:]
+
+
+def test_two_cameras_in_one_loss(gpu, problem):
+    """render_depth keeps what its backward needs: two cameras rendered before one backward give the
+    sum of the two single-camera gradients (snapshot=True); without a snapshot the stale frame raises."""
+    from paper_2201_10887_amd.renderer import Renderer, render_depth
+    s = problem["s"]
+    w = s.work
+    R = Renderer(s.leaves, w.side, w.max_depth, w.cutoff, w.cascades, w.tex_n, w.split_lambda, w.overlap)
+    cams = [s.cam, type(s.cam)(s.cam.pos, s.cam.yaw + 0.4, s.cam.pitch, s.cam.vfov, 256, 192, s.cam.znear)]
+
+    def grads(cam_list, snapshot):
+        v = gpu.tensor(s.leaves["v"], device="cuda", requires_grad=True)
+        sigma = gpu.tensor(s.leaves["sigma"], device="cuda", requires_grad=True)
+        loss = 0.0
+        for c in cam_list:
+            depth, _ = render_depth(v, sigma, R, c, snapshot=snapshot)
+            d = gpu.where(gpu.isfinite(depth), depth, gpu.zeros_like(depth))
+            loss = loss + (d * d).sum() * 1e-6
+        loss.backward()
+        return v.grad.cpu().numpy().astype(np.float64), sigma.grad.cpu().numpy().astype(np.float64)
+
+    g0, g1 = grads([cams[0]], False), grads([cams[1]], False)
+    both = grads(cams, True)
+    for a, b, c in zip(both, g0, g1):
+        err, per = G.grad_close(a, b + c)
+        assert err <= 1e-5 and per.mean() >= 0.9999, (err, per.mean())
+    with pytest.raises(RuntimeError, match="snapshot"):
+        grads(cams, False)

@@ -164,7 +164,8 @@ def standin(gpu, medium):
 def test_maxmip_full_size_bitexact(gpu, medium, standin):
     mip = api.build_maxmip(gpu.as_tensor(standin, device="cuda")).cpu().numpy()
     for k in range(len(standin)):
-        assert np.array_equal(mip[k], omip.flatten(omip.maxmip(standin[k])).astype(np.float32))
+        NN = standin.shape[-1] ** 2  # level 0 is not stored
+        assert np.array_equal(mip[k][NN:], omip.flatten(omip.maxmip(standin[k]))[NN:].astype(np.float32))
 
 
 def test_raycast_full_frame_sampled(gpu, medium, standin):
@@ -192,6 +193,7 @@ def test_long_ray_queue_matches_single_lane_walk(gpu, medium, standin):
     d1, h1 = api.raycast(cam, m["dom"], m["cas"], tex, mip, work=work)
     queued = int(work[0].item())
     assert 1000 < queued < cam.width * cam.height // 20, queued  # long rays exist and were queued
+    assert int(work[1].item()) == 0  # no ray reached the walk's iteration cap (status word)
     d0, d1, h0, h1 = (a.cpu().numpy() for a in (d0, d1, h0, h1))
     fin = np.isfinite(d0)
     assert np.array_equal(fin, np.isfinite(d1))

@@ -55,7 +55,8 @@ def test_maxmip_bitexact(gpu, tiny_scene):
     mip = api.build_maxmip(tex).cpu().numpy()
     for k in range(tex.shape[0]):
         ref = omip.flatten(omip.maxmip(tiny_scene.tex32[k]))
-        assert np.array_equal(mip[k], ref.astype(np.float32))
+        NN = tiny_scene.tex32.shape[-1] ** 2  # level 0 is not stored
+        assert np.array_equal(mip[k][NN:], ref[NN:].astype(np.float32))
 
 
 @pytest.mark.parametrize("N", [2, 4, 32, 64, 128])
@@ -65,7 +66,7 @@ def test_maxmip_small_sizes(gpu, N):
     t[rng.random(t.shape) < 0.1] = -np.inf
     mip = api.build_maxmip(gpu.as_tensor(t, device="cuda")).cpu().numpy()
     for k in range(3):
-        assert np.array_equal(mip[k], omip.flatten(omip.maxmip(t[k])).astype(np.float32))
+        assert np.array_equal(mip[k][N * N:], omip.flatten(omip.maxmip(t[k]))[N * N:].astype(np.float32))
 
 
 def test_raycast_matches_oracle(gpu, tiny_scene):
@@ -91,9 +92,8 @@ def test_full_frame_matches_oracle(gpu, tiny_scene, dev):
     depth, hit = api.raycast(s.cam, s.dom, cas, tex, mip)
     ref = oray.raycast(s.cam, s.dom, s.cascades, s.tex64, threads=8)
     V = float(np.abs(s.leaves["v"]).max())
-    nbad, n = G.compare_hits(depth.cpu().numpy(), hit.cpu().numpy(), ref, s.cam, s.dom, s.cascades, s.tex64,
-                             allow_rate=None, what="tiny full frame", height_tol=1e-5 * V)
-    assert nbad <= 1e-3 * n
+    G.compare_hits(depth.cpu().numpy(), hit.cpu().numpy(), ref, s.cam, s.dom, s.cascades, s.tex64,
+                   allow_rate=1e-5, what="tiny full frame", height_tol=1e-5 * V)
 
 
 def test_raycast_backward_matches_oracle(gpu, tiny_scene):

@@ -131,3 +131,32 @@ def test_renderer_draws_both_surfaces(gpu, two):
     gs = gpu.zeros_like(gv)
     R.backward(two["cam"], cas, gd, gtex, gv, gs, hit=hit)
     assert float(gv.abs().sum()) > 0 and float(R.extra[0]["grad_v"].abs().sum()) > 0
+
+
+def test_nearer_blend_partner_behind_the_drawn_surface(gpu, two):
+    """A second surface 1 mm above the first: in the cascade overlaps its first hit lies in front
+    of the first surface's depth and its blend partner (in the next cascade) often behind it.  The
+    nearer pass must still blend with that partner, as the oracle's cast of the surface on its own
+    does (the adjoint, which walks unclipped, then differentiates the same depth)."""
+    t0 = two["tex32"][0]
+    t1 = np.where(np.isfinite(t0), t0 + np.float32(1e-3), t0).astype(np.float32)
+    cam, dom, cs = two["cam"], two["dom"], two["cs"]
+    rays = [oray.raycast(cam, dom, cs, t) for t in (t0, t1)]
+    tB = rays[1]["val"][:, 4]
+    behind = (rays[1]["rec"][:, 4] >= 0) & (rays[1]["depth"] < rays[0]["depth"]) & (tB > rays[0]["depth"])
+    assert behind.sum() > 50, behind.sum()  # the case occurs on this frame
+    comp = composite.nearest(rays)
+    g0, g1 = gpu.as_tensor(t0, device="cuda"), gpu.as_tensor(t1, device="cuda")
+    depth, hit = api.raycast(cam, dom, two["cas"], g0, api.build_maxmip(g0), work=None)
+    api.raycast_nearer(cam, dom, two["cas"], g1, api.build_maxmip(g1), 1, depth, hit, work=None)
+    dg, hg = depth.cpu().numpy().ravel(), hit.cpu().numpy().ravel().astype(np.int64)
+    sel = np.nonzero(behind & (comp["surface"] == 1))[0]
+    assert np.all((hg[sel] >> composite.SURFACE_SHIFT) == 1)
+    ref = {key: rays[1][key][sel] for key in ("depth", "hit", "dirs")}
+    G.compare_hits(dg[sel], hg[sel] & TAG_MASK, ref, cam, dom, cs, t1, what="surface 1 blended behind surface 0")
+    # the blend moves these depths by up to ~5 cm, below the depth tolerance: check them to FP32 rounding
+    same = (hg[sel] & TAG_MASK) == rays[1]["hit"][sel]
+    assert same.mean() >= 0.99
+    ext = dom.extent
+    assert np.abs(dg[sel][same] - rays[1]["depth"][sel][same]).max() <= 1e-6 * ext
+    assert np.abs(rays[1]["depth"][sel] - rays[1]["val"][sel, 0]).max() > 20e-6 * ext  # blended, not t_A
