@@ -239,55 +239,57 @@ def discretize_work(R, cas, leaves, w, samples=20000) -> dict:
             "mean_influencers": float(np.mean(counts))}
 
 
-def cpu_baseline(w, leaves, cam, R, cas, vis_texels, seconds=12.0):
-    """The FP64 oracle on a bounded sample, single thread, scaled to ms per frame."""
-    from oracle import camera as ocam, discretize as odisc, raycast as oray
-    from oracle.cascades import Cascade
-    from paper_2201_10887_amd import api
-    rng = np.random.default_rng(5)
-    field = odisc.RBFField(leaves, w.cutoff)
-    ocs = [api.CascadeView(c) for c in cas]
-    # discretize leg: random visible-area texels of every cascade
-    K, N = R.K, R.N
-    n_tex = 0
-    t_disc = 0.0
-    while t_disc < seconds / 2:
-        k = int(rng.integers(K))
-        c = ocs[k]
-        poly = c.poly
-        if len(poly) == 0:
-            continue
-        px = rng.uniform(poly[:, 0].min(), poly[:, 0].max(), 2000)
-        py = rng.uniform(poly[:, 1].min(), poly[:, 1].max(), 2000)
-        pts = np.stack([np.clip(px, 0, w.side), np.clip(py, 0, w.side)], axis=1)
-        t0 = time.perf_counter()
-        field.evaluate(pts)
-        t_disc += time.perf_counter() - t0
-        n_tex += len(pts)
-    # ray-casting leg: a random pixel subset over stand-in textures (the raster resampled at the texels)
-    dem = build_scene.dem_cache
-    tex = np.empty((K, N, N))
-    for k, c in enumerate(ocs):
-        gx = np.clip(((c.x0 + np.arange(N) * c.hx) / w.spacing - 0.5).astype(int), 0, dem.shape[0] - 1)
-        gy = np.clip(((c.y0 + np.arange(N) * c.hy) / w.spacing - 0.5).astype(int), 0, dem.shape[0] - 1)
-        tex[k] = dem[np.ix_(gy, gx)]
+def cpu_baseline(w, leaves, cam, R, cas, vis_texels, reps=3):
+    """The FP64 oracle's whole frame on the host cores: its own cascade fit, Eq. 2 at every visible
+    texel of every cascade (the plain-C form, one thread per core), and the ray cast of every pixel
+    over those textures (the plain-C walk).  Median of ``reps`` frames."""
+    from oracle import cascades as ocas, discretize as odisc, raycast as oray
+    threads = _host_threads()
+    times, stage = [], []
+    c_min = float(leaves["c"].min())
     dom = R.dom
-    n_ray = 0
-    t_ray = 0.0
-    while t_ray < seconds / 2:
-        cols = rng.integers(0, cam.width, 4000)
-        rows = rng.integers(0, cam.height, 4000)
-        dirs = ocam.ray_directions(cam, cols, rows)
+    for _ in range(reps):
         t0 = time.perf_counter()
-        oray.cast_rays(np.asarray(cam.pos), dirs, dom, ocs, tex, threads=1)
-        t_ray += time.perf_counter() - t0
-        n_ray += len(dirs)
-    surfaces = 1 + len(R.extra)  # every surface costs the oracle one approximation and one ray cast
-    ms = surfaces * 1e3 * (t_disc / n_tex * vis_texels + t_ray / n_ray * cam.width * cam.height)
-    return {"value": round(ms, 1), "unit": "ms/frame", "cores": 1, "kind": "oracle",
-            "sample": f"{n_tex} texels (Eq. 2, FP64 NumPy) + {n_ray} rays (FP64 C walk over raster-resampled "
-                      f"stand-in textures), one thread, scaled to {vis_texels} visible texels and "
-                      f"{cam.width}x{cam.height} rays" + (f", times {surfaces} surfaces" if surfaces > 1 else "")}
+        cs = ocas.fit_cascades(cam, dom, R.K, R.N, w.split_lambda, w.overlap, c_min)
+        t1 = time.perf_counter()
+        tex = [odisc.discretize_c(c, leaves, dom, w.cutoff, threads=threads) for c in cs]
+        t2 = time.perf_counter()
+        oray.raycast(cam, dom, cs, np.stack(tex), threads=threads)
+        t3 = time.perf_counter()
+        times.append(t3 - t0)
+        stage.append((t1 - t0, t2 - t1, t3 - t2))
+    order = np.argsort(times)
+    mid = int(order[len(order) // 2])
+    surfaces = 1 + len(R.extra)
+    ms = surfaces * times[mid] * 1e3
+    return {"value": round(ms, 1), "unit": "ms/frame", "cores": threads, "kind": "oracle",
+            "cpu": _cpu_model(), "cpu_count": os.cpu_count(),
+            "stage_s": {"fit": round(stage[mid][0], 4), "discretize": round(stage[mid][1], 3),
+                        "raycast": round(stage[mid][2], 3)},
+            "sample": f"the whole {cam.width}x{cam.height} frame ({vis_texels} visible texels over {R.K} x {R.N}^2, "
+                      f"every pixel), FP64 oracle: NumPy fit and visibility, plain-C Eq. 2 and ray walk on "
+                      f"{threads} threads; median of {reps} frames" + (f", times {surfaces} surfaces"
+                                                                        if surfaces > 1 else "")}
+
+
+def _host_threads() -> int:
+    """Host threads for the oracle: the CPUs this process may run on, at most 16 (one GPU's share of a box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def fit_tau(dem, side, depth, target, rel=0.15, iters=24):
@@ -308,49 +310,61 @@ def fit_tau(dem, side, depth, target, rel=0.15, iters=24):
     return best[0]
 
 
-def build_batch_scene(n_fields=8, n_views=64, seed=1004, budget_texels=1 << 28):
-    """8 fBm heightfields of uneven size and 64 views of them (seeded)."""
-    from paper_2201_10887_amd import api, autotune, synth
-    from paper_2201_10887_amd.batch import BatchRenderer, Field, ViewSpec
+def build_batch_fields(n_fields=8, n_views=64, seed=1004):
+    """8 fBm heightfields of uneven size and 64 cameras on them (seeded)."""
+    from paper_2201_10887_amd import api, synth
+    from paper_2201_10887_amd.batch import Field
     t0 = time.time()
     fspecs = synth.batch_fields(n_fields, seed)
     vspecs = synth.batch_views(n_views, n_fields, seed)
     dems, fields = [], []
-    for f in fspecs:
+    for f, tau in zip(fspecs, synth.BATCH_TAU):
         dem = synth.fbm_dem(f.dem_n, f.octaves, 0.8, f.seed)
-        tau = fit_tau(dem, f.side, f.depth, f.target_leaves)
         leaves = api.build_quadtree(dem, f.side, f.depth, tau)
         leaves["sigma"] = np.ones(len(leaves["x"]), np.float32)
         dems.append(dem)
         fields.append(Field(leaves, f.side, f.depth, 3.5))
     cams = synth.batch_cameras(dems, fspecs, vspecs, seed)
+    print(f"[bench] batch fields: {', '.join(str(f.n) for f in fields)} leaves, {n_views} views, built in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    return fields, vspecs, cams
+
+
+def batch_renderer(fields, vspecs, budget_texels):
+    """The batch's buffers and plan with N per view from the texel budget."""
+    from paper_2201_10887_amd import autotune
+    from paper_2201_10887_amd.batch import BatchRenderer, ViewSpec
     ns = autotune.texel_budget([(v.width, v.height, v.K) for v in vspecs], budget_texels)
     specs = [ViewSpec(v.field, v.K, n, v.width, v.height, 0.5, 0.05) for v, n in zip(vspecs, ns)]
-    R = BatchRenderer(fields, specs, backward=True)
-    R.set_cameras(cams)
-    print(f"[bench] batch scene: {n_fields} fields ({', '.join(str(f.n) for f in fields)} leaves), {n_views} views, "
-          f"{sum(s.K * s.N * s.N for s in specs)} texels, built in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
-    return R, cams
+    return BatchRenderer(fields, specs, backward=True)
 
 
 def batch_main(args):
     """Many views of many heightfields: one batched launch set (captured as a graph) against
-    the same views rendered one by one through the per-view entry points."""
+    the same views rendered one by one through the per-view entry points.  The texel budget is
+    chosen by measurement (the largest whose tuned forward + backward step fits the target)."""
     import torch
     from paper_2201_10887_amd import api, autotune
-    R, cams = build_batch_scene()
-    stream = torch.cuda.current_stream()
+    fields, vspecs, cams = build_batch_fields()
     gen = torch.Generator(device="cuda").manual_seed(1004)
-    R.forward()
-    for b in R.bufs:
-        d = b["depth"]
-        b["grad_depth"].copy_(torch.where(torch.isfinite(d), torch.randn(d.shape, generator=gen, device="cuda"),
-                                          torch.zeros_like(d)))
-    tuned = autotune.tune(R, cams, backward=True,
-                          log=lambda m: print(m, file=sys.stderr, flush=True) if args.verbose else None)
-    print(f"[bench] tuning {tuned['tuning']} ({'cached' if tuned['cached'] else 'measured'})", file=sys.stderr,
+    log = (lambda m: print(m, file=sys.stderr, flush=True)) if args.verbose else None
+
+    def build(budget):
+        R = batch_renderer(fields, vspecs, budget)
+        R.set_cameras(cams)
+        R.forward()
+        for b in R.bufs:
+            d = b["depth"]
+            b["grad_depth"].copy_(torch.where(torch.isfinite(d), torch.randn(d.shape, generator=gen, device="cuda"),
+                                              torch.zeros_like(d)))
+        return R
+
+    chosen = autotune.tune_budget(build, cams, args.batch_target_ms, backward=True, log=log)
+    R = chosen["renderer"]
+    tuned = {"tuning": R.tuning}
+    print(f"[bench] texel budget {chosen['budget']} ({chosen['curve']}), tuning {R.tuning}", file=sys.stderr,
           flush=True)
+    stream = torch.cuda.current_stream()
 
     def train():
         R.forward()
@@ -405,15 +419,15 @@ def batch_main(args):
         "vs_baseline": None,
         "dtype": "f32 texels, f64 ray geometry",
         "data": "synthetic (seeded fBm terrain)",
-        "config": {"workload": "batch: 8 fBm heightfields (10k-1.5M leaves, depth 8-12), 64 views "
-                               "(256^2 to 1080p, K 2-4, texel budget 2^28)",
+        "config": {"workload": f"batch: 8 fBm heightfields (9k-1.64M leaves, depth 8-12), 64 views "
+                               f"(256^2 to 1080p, K 2-4), texel budget tuned to a {args.batch_target_ms} ms step",
                    "fields": [f.n for f in R.fields], "views": R.n_views, "texels": texels, "rays": rays},
         "ms": {k: round(v, 4) for k, v in ms.items()},
         "speedup_vs_per_view": {"fwd": round(ms["per_view_fwd"] / ms["graph_fwd"], 3),
                                 "fwd_bwd": round(ms["per_view_fwd_bwd"] / ms["graph_fwd_bwd"], 3)},
         "grays_per_s_fwd": round(rays / (ms["graph_fwd"] * 1e-3) / 1e9, 3),
+        "texel_budget": {"chosen": chosen["budget"], "target_ms": chosen["target_ms"], "curve": chosen["curve"]},
         "tuning": tuned["tuning"],
-        "tuning_cached": tuned["cached"],
     }
     print(json.dumps(out), flush=True)
 
@@ -425,10 +439,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle frames timed for the CPU baseline (median)")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--batch-target-ms", type=float, default=33.3,
+                    help="batch workload: time target of one forward + backward step for the texel budget tuner")
     ap.add_argument("--skip-flight", action="store_true",
                     help="skip the texel-reuse flight (profiled runs: its launches differ from a frame's)")
+    ap.add_argument("--skip-startup", action="store_true",
+                    help="skip the start-up measurements (device quadtree, influence lists)")
+    ap.add_argument("--per-cascade", action="store_true",
+                    help="also time discretize with each cascade launched alone (counter runs per cascade)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (known traffic) to calibrate hardware byte counters")
     args = ap.parse_args()
@@ -513,6 +533,11 @@ def main():
             "build_maxmip_water": lambda: api.build_maxmip(X["tex"], X["mip"]),
             "raycast_nearer_water": nearer,
         })
+    if args.per_cascade:  # each cascade in a launch of its own
+        for k in range(R.K):
+            one = (api.Cascade * 1)(cas[k])
+            stage[f"discretize_cascade{k}"] = (lambda one=one, k=k: api.discretize(R.L, R.dom, one, R.tex[k:k + 1],
+                                                                                   R.mask[k:k + 1]))
     stage_ms = {k: timed(f, args.steps, stream) for k, f in stage.items()}
     del Lw, tex_w
     api.discretize(R.L, R.dom, cas, R.tex, R.mask)
@@ -522,7 +547,7 @@ def main():
         R.fit(cam)
     fit_us = (time.perf_counter() - t_host) * 1e4
 
-    startup = startup_ms(R, dem, w)
+    startup = None if args.skip_startup else startup_ms(R, dem, w)
     work = discretize_work(R, cas, leaves, w)
     reuse = None if args.skip_flight else texel_reuse_flight(R, cam, depth, hit)
     print(f"[bench] texel reuse along a flight: {reuse}", file=sys.stderr, flush=True)
@@ -551,7 +576,8 @@ def main():
                  "algorithmic_flops_per_launch": round(work["flops"] / launches), "algorithmic_bytes_per_launch":
                  round(work["bytes"] / launches), "hbm_frac": round(t_hbm_floor / t_disc, 4),
                  "alu_frac": round(t_alu_floor / t_disc, 4)})
-    mip_bytes = K * (R.N * R.N * 4 + api.mip_size(R.N) * 4)
+    # max-mipmap: each texel read once (4 B), levels 1 .. log2 N written (level 0 is not stored)
+    mip_bytes = K * (R.N * R.N * 4 + (api.mip_size(R.N) - R.N * R.N) * 4)
     dominant = max(("discretize", "build_maxmip", "raycast"), key=lambda k: stage_ms[k])
     out = {
         "metric": "ms/frame at 1080p (Gtexel/s, Grays/s, %HBM roofline); fwd+bwd vs fwd time",
@@ -585,6 +611,9 @@ def main():
         "pairs": round(pairs),
         "mean_influencers": round(work["mean_influencers"], 2),
         "maxmip_hbm_frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "maxmip_roofline": {"bound": "hbm", "achieved": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic_bytes": mip_bytes,
+                            "frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "dominant_stage": dominant,
         "roofline": roof,
     }
@@ -600,7 +629,7 @@ def main():
                                           "of GB; the per-texel and per-ray oracle costs are those of the medium scene"}
     elif not args.no_cpu_baseline:
         try:
-            out["cpu_baseline"] = cpu_baseline(w, leaves, cam, R, cas, vis_texels, args.cpu_seconds)
+            out["cpu_baseline"] = cpu_baseline(w, leaves, cam, R, cas, vis_texels, args.cpu_reps)
         except Exception as e:  # the baseline is reported, not required
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)

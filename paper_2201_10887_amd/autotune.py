@@ -8,7 +8,9 @@ halved view by view (largest N first) until the batch's sum of K N^2 fits the
 budget.  ``tune`` times every launch shape of a grid on the actual batch
 (forward, or forward + backward) with HIP events and keeps the fastest; the
 choice is cached in a JSON file keyed by the batch's shape and the device,
-so a later run with the same shape skips the measurements.
+so a later run with the same shape skips the measurements.  ``tune_budget``
+chooses the texel budget itself by measurement: the largest budget of a
+ladder whose tuned batch step fits a time target.
 """
 from __future__ import annotations
 
@@ -125,3 +127,41 @@ def tune(renderer, cams: Sequence, backward: bool = True, grid: Optional[Dict[st
     entry = dict(entry)
     entry["cached"] = False
     return entry
+
+
+BUDGET_LADDER = (1 << 26, 1 << 27, 1 << 28, 1 << 29)
+
+
+def tune_budget(build, cams: Sequence, target_ms: float, budgets: Sequence[int] = BUDGET_LADDER,
+                backward: bool = True, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, log=None) -> dict:
+    """Choose the cascade texel budget of a batch by measurement: the largest budget of the ladder whose
+    batch step (forward, and with ``backward`` the backward pass too; launch shape tuned by ``tune`` at
+    each budget) fits ``target_ms``, i.e. the finest cascades the batch affords in its time.  ``build(budget)``
+    returns a ``BatchRenderer`` whose views take N from ``texel_budget(..., budget)``.  Returns
+    ``{"budget", "renderer", "ms", "curve"}`` (the smallest budget when none fits); every renderer but the
+    chosen one is released."""
+    import torch
+    curve, chosen = [], None
+    for budget in sorted(budgets):
+        R = build(budget)
+        tuned = tune(R, cams, backward=backward, reps=reps, cache_path=cache_path, log=log)
+        R.set_cameras(cams)
+
+        def step():
+            R.forward()
+            if backward:
+                R.backward()
+
+        ms = _time_ms(step, reps)
+        texels = sum(s.K * s.N * s.N for s in R.specs)
+        curve.append({"budget": budget, "texels": texels, "ms": round(ms, 4), "tuning": tuned["tuning"]})
+        if log:
+            log(f"[autotune] budget 2^{budget.bit_length() - 1}: {texels} texels, {ms:.3f} ms")
+        if chosen is None or ms <= target_ms:
+            chosen = (budget, R, ms)  # the previous choice's buffers go with its last reference
+        else:
+            del R
+            break  # larger budgets only take longer
+        torch.cuda.empty_cache()
+    return {"budget": chosen[0], "renderer": chosen[1], "ms": round(chosen[2], 4), "target_ms": target_ms,
+            "curve": curve}

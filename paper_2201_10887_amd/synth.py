@@ -345,6 +345,12 @@ class BatchViewSpec:
     K: int
 
 
+# Refinement thresholds of the eight batch fields (seed 1004): bisected once, on a log scale, until the
+# quadtree's leaf count came within 15 % of each field's drawn target (9055, 19666, 21883, 105007, 437497,
+# 1639447, 23554 and 272578 leaves).
+BATCH_TAU = (6.97831, 6.97831, 5.62341, 2.37137, 1.71544, 0.897687, 5.04807, 2.12875)
+
+
 def batch_fields(n_fields: int = 8, seed: int = 1004, lo: float = 1e4, hi: float = 4e6) -> List[BatchFieldSpec]:
     rng = np.random.default_rng(seed)
     out = []
