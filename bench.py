@@ -613,7 +613,10 @@ def main():
         "maxmip_hbm_frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "maxmip_roofline": {"bound": "hbm", "achieved": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic_bytes": mip_bytes,
-                            "frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                            "frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "traffic": (recorded_traffic("paper_2201_10887_amd/csrc/hfr_maxmip.hip",
+                                                         "profiles/maxmip_kernel_medium_hbm_counters.md")
+                                        if args.workload == "medium" else None)},
         "dominant_stage": dominant,
         "roofline": roof,
     }

@@ -196,12 +196,19 @@ __device__ void small_body(const float* __restrict__ tk, float* __restrict__ mk,
 
 __device__ inline int64_t pyramid_size(int N) { return (4 * (int64_t)N * N - 1) / 3; }
 
+// One workgroup per 64 x 64-cell tile of the K cascades, stacked as K * N / 64
+// tile rows.  The XCD-aware mapping hands each XCD a contiguous run of tile
+// rows: the texel column and row a tile shares with its right and lower
+// neighbours (its 65th) then sit in the same L2 as the neighbour's own read.
 __global__ __launch_bounds__(256) void maxmip_tile_kernel(const float* __restrict__ tex, float* __restrict__ mip,
-                                                          int N)
+                                                          int N, int K)
 {
     __shared__ TileShared sh;
-    const int k = blockIdx.z;
-    tile_body(tex + (int64_t)k * N * N, mip + k * pyramid_size(N), N, blockIdx.x, blockIdx.y, sh);
+    const int g = N / MT;
+    int tx, trow;
+    xcd_tile(blockIdx.x, g, g * K, &tx, &trow);
+    const int k = trow / g;
+    tile_body(tex + (int64_t)k * N * N, mip + k * pyramid_size(N), N, tx, trow - k * g, sh);
 }
 
 __global__ __launch_bounds__(256) void maxmip_top_kernel(float* __restrict__ mip, int N)
@@ -296,7 +303,7 @@ extern "C" hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, f
         HFR_LAUNCH_CHECK("build_maxmip");
         return hfr_ok();
     }
-    maxmip_tile_kernel<<<dim3(N / MT, N / MT, K), dim3(256), 0, s>>>(tex, mip, N);
+    maxmip_tile_kernel<<<dim3((N / MT) * (N / MT) * K), dim3(256), 0, s>>>(tex, mip, N, K);
     HFR_LAUNCH_CHECK("build_maxmip");
     maxmip_top_kernel<<<dim3(K), dim3(256), 0, s>>>(mip, N);
     HFR_LAUNCH_CHECK("build_maxmip (top levels)");
