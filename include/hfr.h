@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 10
+#define HFR_ABI_VERSION 11
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -461,13 +461,14 @@ hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
  * workgroups take work from per-XCD queues and steal from other queues when
  * theirs is empty, so views of uneven size share the GPU without a launch
  * per view.  The per-view work is the same as hfr_discretize,
- * hfr_build_maxmip and hfr_raycast without a long-ray queue (work = NULL;
- * bit-identical outputs) and their adjoints; the batch is not in the paper,
+ * hfr_build_maxmip and hfr_raycast (bit-identical outputs, with or without
+ * the long-ray queue) and their adjoints; the batch is not in the paper,
  * which renders one view per frame.
  *
  * The plan is a library-owned host object holding device copies of the
- * field and view descriptors (allocated by hfr_batch_plan_create, the only
- * call that allocates); every buffer it names stays caller-owned and must
+ * field and view descriptors and the long-ray queue (4 B per pixel per 4
+ * pixels, allocated by hfr_batch_plan_create, the only call that
+ * allocates); every buffer it names stays caller-owned and must
  * outlive the plan.  hfr_batch_launch and hfr_batch_launch_backward
  * allocate nothing, issue no memset and no host synchronisation, and read
  * every per-camera value from device memory, so both may be captured into
@@ -516,12 +517,18 @@ typedef struct {
  * a wave takes at a time (8, 16, 32 or 64; height 64 / ray_tile_w).
  * disc_grain: 16 x 16 texel blocks a discretize workgroup takes per queue
  * access, in [1, 64] (small runs keep the blocks running at once close
- * together, large runs need fewer atomics).  Defaults: 4, 4, 32, 8. */
+ * together, large runs need fewer atomics).  ray_queue: 1 = hfr_raycast's
+ * long-ray queue for the batch (a ray still walking after 64 steps is queued
+ * and finished by a second launch with 16 lanes per ray; the plan holds room
+ * for a quarter of each view's pixels and a ray past that finishes in the
+ * first launch), 0 = every ray finishes in the first launch; outputs are the
+ * same either way.  Defaults: 4, 4, 32, 8, 0. */
 typedef struct {
     int32_t disc_blocks_per_cu;
     int32_t ray_blocks_per_cu;
     int32_t ray_tile_w;
     int32_t disc_grain;
+    int32_t ray_queue;
 } hfr_batch_tuning;
 
 /* Validates the fields and views, copies their descriptors to device memory
@@ -551,6 +558,13 @@ hfr_status hfr_batch_set_cameras(hfr_batch_plan* plan, const hfr_camera* cams, h
 /* Copies view `view`'s cascades from the last hfr_batch_set_cameras into the
  * host array out[K]. */
 hfr_status hfr_batch_cascades(const hfr_batch_plan* plan, int32_t view, hfr_cascade* out);
+
+/* Rays of each view that the last ray-cast launch of the plan (forward or
+ * backward) with ray_queue = 1 sent to the long-ray queue, into the host
+ * array out[n_views] (may exceed the view's room of a quarter of its
+ * pixels: the rest finished in place).  Synchronises the device; not to be
+ * captured. */
+hfr_status hfr_batch_long_rays(const hfr_batch_plan* plan, int32_t* out);
 
 /* Forward pass of every view: textures, masks, max-mipmaps, depth and hit
  * images, as hfr_discretize + hfr_build_maxmip + hfr_raycast would write

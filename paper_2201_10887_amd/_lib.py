@@ -68,7 +68,7 @@ class BatchView(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("disc_blocks_per_cu", ctypes.c_int32), ("ray_blocks_per_cu", ctypes.c_int32),
-                ("ray_tile_w", ctypes.c_int32), ("disc_grain", ctypes.c_int32)]
+                ("ray_tile_w", ctypes.c_int32), ("disc_grain", ctypes.c_int32), ("ray_queue", ctypes.c_int32)]
 
 
 P = ctypes.c_void_p
@@ -113,6 +113,7 @@ SIGNATURES = {
     "hfr_batch_plan_create": ([PP(BatchField), I32, PP(BatchView), I32, PP(P)], I32),
     "hfr_batch_plan_destroy": ([P], None),
     "hfr_batch_set_tuning": ([P, PP(BatchTuning)], I32),
+    "hfr_batch_long_rays": ([P, P], I32),
     "hfr_batch_set_cameras": ([P, PP(Camera), P], I32),
     "hfr_batch_cascades": ([P, I32, PP(Cascade)], I32),
     "hfr_batch_launch": ([P, P], I32),

@@ -541,9 +541,17 @@ def batch_plan_destroy(plan: BatchPlan) -> None:
 
 
 def batch_set_tuning(plan: BatchPlan, disc_blocks_per_cu: int = 4, ray_blocks_per_cu: int = 4,
-                     ray_tile_w: int = 32, disc_grain: int = 8) -> None:
-    t = _lib.BatchTuning(int(disc_blocks_per_cu), int(ray_blocks_per_cu), int(ray_tile_w), int(disc_grain))
+                     ray_tile_w: int = 32, disc_grain: int = 8, ray_queue: int = 0) -> None:
+    t = _lib.BatchTuning(int(disc_blocks_per_cu), int(ray_blocks_per_cu), int(ray_tile_w), int(disc_grain),
+                         int(ray_queue))
     call("hfr_batch_set_tuning", plan.handle, ctypes.byref(t))
+
+
+def batch_long_rays(plan: BatchPlan) -> np.ndarray:
+    """Rays per view that the plan's last ray-cast launch sent to the long-ray queue (synchronises)."""
+    out = np.zeros(plan.n_views, np.int32)
+    call("hfr_batch_long_rays", plan.handle, out.ctypes.data_as(ctypes.c_void_p))
+    return out
 
 
 def batch_set_cameras(plan: BatchPlan, cams: Sequence, stream=None) -> None:

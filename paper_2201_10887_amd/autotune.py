@@ -28,6 +28,7 @@ DEFAULT_GRID = {
     "disc_grain": (4, 8, 16),
     "ray_blocks_per_cu": (2, 4),
     "ray_tile_w": (8, 16, 32),
+    "ray_queue": (0, 1),
 }
 
 

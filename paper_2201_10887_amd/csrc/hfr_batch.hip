@@ -8,9 +8,11 @@
 //    texel blocks of all cascades of all views (per-XCD queues);
 //  - max-mipmap: one launch over the 64 x 64-cell tiles of all cascades, one for their top levels;
 //  - ray casting and its adjoint: one persistent launch over all 64-pixel
-//    tiles of all views, taken wave by wave.
+//    tiles of all views, taken wave by wave; optionally (tuning.ray_queue)
+//    the long rays of every view finish in a second launch, 16 lanes each.
 // Every per-camera value (cascades, ray setup) lives in device memory, so
 // the launch sequence can be captured once and replayed for new cameras.
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -70,6 +72,7 @@ hfr_status check_tuning(const hfr_batch_tuning& t)
     HFR_REQUIRE(t.ray_tile_w == 8 || t.ray_tile_w == 16 || t.ray_tile_w == 32 || t.ray_tile_w == 64,
                 "ray_tile_w %d is not 8, 16, 32 or 64", t.ray_tile_w);
     HFR_REQUIRE(t.disc_grain >= 1 && t.disc_grain <= 64, "disc_grain %d outside [1, 64]", t.disc_grain);
+    HFR_REQUIRE(t.ray_queue == 0 || t.ray_queue == 1, "ray_queue %d is not 0 or 1", t.ray_queue);
     return HFR_OK;
 }
 
@@ -85,7 +88,8 @@ struct hfr_batch_plan {
     std::vector<hfr_cascade> cas;   // from the last hfr_batch_set_cameras
     std::vector<int> tex_start, mip_start, ray_start;
     int pass_blocks[HFR_MIP_PASSES] = {};
-    hfr_batch_tuning tuning{4, 4, 32, 8};
+    hfr_batch_tuning tuning{4, 4, 32, 8, 0};
+    int tail_blocks = 64;            // workgroups of the long-ray launch
     bool cameras_set = false, backward_ok = false, upload_pending = false;
     // pinned staging of the per-camera descriptors
     BatchTex* tex_h = nullptr;
@@ -96,6 +100,7 @@ struct hfr_batch_plan {
     BatchTex* tex_d = nullptr;
     BatchView* views_d = nullptr;
     int *tex_start_d = nullptr, *mip_start_d = nullptr, *ray_start_d = nullptr, *queues_d = nullptr;
+    int *rayq_d = nullptr, *rayq_count_d = nullptr;
     BatchDev P{};
 };
 
@@ -111,6 +116,8 @@ void release(hfr_batch_plan* q)
     (void)hipFree(q->mip_start_d);
     (void)hipFree(q->ray_start_d);
     (void)hipFree(q->queues_d);
+    (void)hipFree(q->rayq_d);
+    (void)hipFree(q->rayq_count_d);
     if (q->tex_h) (void)hipHostFree(q->tex_h);
     if (q->views_h) (void)hipHostFree(q->views_h);
     if (q->upload_done) (void)hipEventDestroy(q->upload_done);
@@ -219,6 +226,7 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     q->tex_start.assign(n_tex + 1, 0);
     q->mip_start.assign(HFR_MIP_PASSES * (n_tex + 1), 0);
     q->cas_off.assign(n_views + 1, 0);
+    int64_t rayq_total = 0;  // long-ray queue: a quarter of each view's pixels (a ray past that finishes in place)
     int t = 0;
     for (int v = 0; v < n_views; ++v) {
         const hfr_batch_view& V = views[v];
@@ -243,6 +251,9 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
             }
         }
         BatchView& bv = q->views_h[v];
+        bv.q_off = (int)rayq_total;
+        bv.q_cap = (int)std::max<int64_t>(64, (int64_t)V.width * V.height / 4);
+        rayq_total += bv.q_cap;
         bv.tex = V.tex;
         bv.mip = V.mip;
         bv.depth = V.depth;
@@ -264,6 +275,9 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     if (st == HFR_OK) st = dev_alloc(&q->mip_start_d, q->mip_start.size());
     if (st == HFR_OK) st = dev_alloc(&q->ray_start_d, q->ray_start.size());
     if (st == HFR_OK) st = dev_alloc(&q->queues_d, HFR_QUEUE_WORDS);
+    if (st == HFR_OK && rayq_total >= MAX_WORK) st = hfr_fail(HFR_EINVAL, "too many pixels in the batch");
+    if (st == HFR_OK) st = dev_alloc(&q->rayq_d, rayq_total);
+    if (st == HFR_OK) st = dev_alloc(&q->rayq_count_d, n_views);
     if (st != HFR_OK) {
         release(q);
         return st;
@@ -280,7 +294,12 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
         return hfr_fail(HFR_EDEVICE, "plan upload: %s", hipGetErrorString(e));
     }
     q->P = BatchDev{q->fields_d, q->tex_d, q->tex_start_d, q->mip_start_d, q->views_d, q->ray_start_d, q->queues_d,
-                    (int)n_tex, n_views, q->tuning.ray_tile_w, q->tuning.disc_grain};
+                    q->rayq_d, q->rayq_count_d, (int)n_tex, n_views, q->tuning.ray_tile_w, q->tuning.disc_grain,
+                    q->tuning.ray_queue};
+    // the long-ray launch: enough lane groups that a typical queue is taken in one round
+    int64_t pixels = 0;
+    for (int v = 0; v < n_views; ++v) pixels += (int64_t)views[v].width * views[v].height;
+    q->tail_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(64, pixels / 1024));
     *out = q;
     return hfr_ok();
 }
@@ -315,6 +334,7 @@ extern "C" hfr_status hfr_batch_set_tuning(hfr_batch_plan* plan, const hfr_batch
     if (e != hipSuccess) return hfr_fail(HFR_EDEVICE, "tuning upload: %s", hipGetErrorString(e));
     plan->P.tile_w = tuning->ray_tile_w;
     plan->P.disc_grain = tuning->disc_grain;
+    plan->P.ray_queue = tuning->ray_queue;
     return hfr_ok();
 }
 
@@ -363,6 +383,16 @@ extern "C" hfr_status hfr_batch_cascades(const hfr_batch_plan* plan, int32_t vie
     return hfr_ok();
 }
 
+extern "C" hfr_status hfr_batch_long_rays(const hfr_batch_plan* plan, int32_t* out)
+{
+    HFR_REQUIRE(plan != nullptr && out != nullptr, "plan or out is NULL");
+    const int nv = plan->P.n_views;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(out, plan->rayq_count_d, nv * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hfr_fail(HFR_EDEVICE, "reading the long-ray counts: %s", hipGetErrorString(e));
+    return hfr_ok();
+}
+
 extern "C" hfr_status hfr_batch_launch(const hfr_batch_plan* plan, hfr_stream stream)
 {
     HFR_REQUIRE(plan != nullptr, "plan is NULL");
@@ -370,9 +400,15 @@ extern "C" hfr_status hfr_batch_launch(const hfr_batch_plan* plan, hfr_stream st
     hipStream_t s = (hipStream_t)stream;
     zero_ints_kernel<<<1, 64, 0, s>>>(plan->queues_d, HFR_QUEUE_WORDS);
     HFR_LAUNCH_CHECK("batch queue reset");
+    if (plan->P.ray_queue) {
+        const int nv = plan->P.n_views;
+        zero_ints_kernel<<<(nv + 255) / 256, 256, 0, s>>>(plan->rayq_count_d, nv);
+        HFR_LAUNCH_CHECK("batch long-ray queue reset");
+    }
     hfr_status st = launch_discretize_batch(plan->P, plan->cus * plan->tuning.disc_blocks_per_cu, false, s);
     if (st == HFR_OK) st = launch_maxmip_batch(plan->P, plan->pass_blocks, s);
-    if (st == HFR_OK) st = launch_raycast_batch(plan->P, plan->cus * plan->tuning.ray_blocks_per_cu, false, s);
+    if (st == HFR_OK)
+        st = launch_raycast_batch(plan->P, plan->cus * plan->tuning.ray_blocks_per_cu, plan->tail_blocks, false, s);
     return st == HFR_OK ? hfr_ok() : st;
 }
 
@@ -388,7 +424,13 @@ extern "C" hfr_status hfr_batch_launch_backward(const hfr_batch_plan* plan, hfr_
     const int nf = (int)plan->fields.size();
     zero_grads_kernel<<<dim3(64, plan->P.n_tex + nf), dim3(256), 0, s>>>(plan->P, nf);
     HFR_LAUNCH_CHECK("batch gradient reset");
-    hfr_status st = launch_raycast_batch(plan->P, plan->cus * plan->tuning.ray_blocks_per_cu, true, s);
+    if (plan->P.ray_queue) {
+        const int nv = plan->P.n_views;
+        zero_ints_kernel<<<(nv + 255) / 256, 256, 0, s>>>(plan->rayq_count_d, nv);
+        HFR_LAUNCH_CHECK("batch long-ray queue reset");
+    }
+    hfr_status st =
+        launch_raycast_batch(plan->P, plan->cus * plan->tuning.ray_blocks_per_cu, plan->tail_blocks, true, s);
     if (st == HFR_OK) st = launch_discretize_batch(plan->P, plan->cus * plan->tuning.disc_blocks_per_cu, true, s);
     return st == HFR_OK ? hfr_ok() : st;
 }

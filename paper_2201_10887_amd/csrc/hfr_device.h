@@ -184,6 +184,7 @@ struct BatchView {
     const float* gdepth;
     float* gtex;
     int tiles_x;       // 64-pixel tiles per image row
+    int q_off, q_cap;  // the view's slice of the plan's long-ray queue (pixel indices)
 };
 
 constexpr int HFR_QUEUE_DISC = 0, HFR_QUEUE_RAY = 8, HFR_QUEUE_RAY_BWD = 16, HFR_QUEUE_DISC_BWD = 24;
@@ -198,8 +199,11 @@ struct BatchDev {
     const BatchView* views;
     const int* ray_start;  // [n_views + 1] prefix sums of 64-pixel tiles
     int* queues;           // HFR_QUEUE_WORDS counters, zeroed before each persistent launch
+    int* rayq;             // long-ray queue: each view's slice [q_off, q_off + q_cap) holds pixel indices
+    int* rayq_count;       // [n_views] rays queued per view, zeroed before each ray-cast launch
     int n_tex, n_views, tile_w;
     int disc_grain;        // texel blocks per discretize queue access
+    int ray_queue;         // 1: rays past the step budget go to the queue, then a lane-group launch
 };
 
 // Read-only view of descriptor memory through the constant address space: the
@@ -214,7 +218,7 @@ __device__ inline const T& as_constant(const T* p, int i)
 
 hfr_status launch_discretize_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s);
 hfr_status launch_maxmip_batch(const BatchDev& P, const int* pass_blocks, hipStream_t s);
-hfr_status launch_raycast_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s);
+hfr_status launch_raycast_batch(const BatchDev& P, int blocks, int tail_blocks, bool backward, hipStream_t s);
 
 // Next range of work indices from a set of 8 queues that split [0, total)
 // into 8 contiguous chunks, one per XCD (the hardware deals workgroups to

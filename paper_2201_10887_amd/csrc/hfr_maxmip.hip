@@ -232,9 +232,10 @@ __device__ __host__ inline int pass_tiles(int N, int p)
     return N > MT ? 1 : 0;
 }
 
-// Pass p over every cascade of a batch: workgroup b takes the MIP_GRAIN
-// consecutive tiles [b MIP_GRAIN, (b + 1) MIP_GRAIN) of the pass's tile list
-// (one search, then a forward walk over the cascades).
+// Pass p over every cascade of a batch: workgroup b takes run r of MIP_GRAIN
+// consecutive tiles [r MIP_GRAIN, (r + 1) MIP_GRAIN) of the pass's tile list
+// (one search, then a forward walk over the cascades), where r runs
+// contiguously within each XCD (the tile pass's neighbours share an L2).
 constexpr int MIP_GRAIN = 4;
 
 union Pass0Shared {
@@ -247,7 +248,9 @@ __global__ __launch_bounds__(256) void maxmip_batch_kernel(BatchDev P, int total
 {
     __shared__ typename std::conditional<PASS == 0, Pass0Shared, TopShared>::type sh;
     const int* start = P.mip_start + PASS * (P.n_tex + 1);
-    const int w0 = blockIdx.x * MIP_GRAIN, w1 = min(w0 + MIP_GRAIN, total);
+    int run, unused;
+    xcd_tile(blockIdx.x, gridDim.x, 1, &run, &unused);
+    const int w0 = run * MIP_GRAIN, w1 = min(w0 + MIP_GRAIN, total);
     int item = find_item(start, P.n_tex, w0);
     int lo = start[item], hi = start[item + 1];
     for (int w = w0; w < w1; ++w) {

@@ -640,6 +640,11 @@ __global__ void zero_queue_kernel(int* __restrict__ work)
 // Persistent form over every view of a batch: each wave takes runs of
 // 64-pixel tiles (tile_w x 64 / tile_w; guided: up to 32 early, down to 1 at
 // the end) from the queues until all are done; waves never wait for each other.
+// With P.ray_queue a pixel whose walk exceeds RAY_BUDGET steps goes to its
+// view's slice of the long-ray queue (one reservation per wave and tile, as
+// in the frame kernel); a pixel that finds the slice full is walked again to
+// the end by the whole wave at once (lanes without such a pixel walk
+// nothing), so the adjoint's shuffles see every lane.
 
 template <bool BACKWARD>
 __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
@@ -669,9 +674,55 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
             const BatchView& V = as_constant(P.views, v);
             const int local = w - v_lo;
             const int tx = local % V.tiles_x, ty = local / V.tiles_x;
-            raycast_pixel<BACKWARD, 1>(V.A, tx * tw + lane % tw, ty * th + lane / tw, V.tex, V.mip, V.depth, V.hit,
-                                       V.gdepth, V.gtex, 0, INT_MAX, SurfaceArgs{0, false, nullptr, nullptr});
+            const int col = tx * tw + lane % tw, row = ty * th + lane / tw;
+            const SurfaceArgs S{0, false, nullptr, nullptr};
+            const bool deferred = raycast_pixel<BACKWARD, 1>(V.A, col, row, V.tex, V.mip, V.depth, V.hit, V.gdepth,
+                                                             V.gtex, 0, P.ray_queue ? RAY_BUDGET : INT_MAX, S);
+            const uint64_t m = __ballot(deferred);
+            if (!m) continue;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&P.rayq_count[v], __popcll(m));
+            base = __shfl(base, leader);
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            const int slot = base + __popcll(m & lt);
+            const bool fits = slot < V.q_cap;
+            if (deferred && fits) P.rayq[V.q_off + slot] = row * V.A.W + col;
+            const bool again = deferred && !fits;
+            if (__ballot(again))
+                raycast_pixel<BACKWARD, 1>(V.A, again ? col : V.A.W, again ? row : V.A.H, V.tex, V.mip, V.depth, V.hit,
+                                           V.gdepth, V.gtex, 0, INT_MAX, S);
         }
+    }
+}
+
+// The batch's queued long rays, RAY_SPLIT lanes each (as raycast_tail_kernel):
+// the queue is complete when this kernel starts.  Views are taken in order,
+// every wave walking each view's entries with a grid stride; the entries of
+// all views are numbered consecutively (each view's count rounded up to whole
+// waves' worth), so the waves' shares stay even across views.
+template <bool BACKWARD>
+__global__ __launch_bounds__(256) void raycast_batch_tail_kernel(BatchDev P)
+{
+    constexpr int G = RAY_SPLIT, PER_WAVE = 64 / G;
+    const int lane = __lane_id(), s = lane & (G - 1);
+    const int waves = (int)(gridDim.x * (blockDim.x / 64));
+    const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+    const int stride = waves * PER_WAVE;
+    int64_t before = 0;  // entries of the views already passed, in whole waves' worth
+    for (int v = 0; v < P.n_views; ++v) {
+        const BatchView& V = as_constant(P.views, v);
+        const int count = min(__builtin_amdgcn_readfirstlane(P.rayq_count[v]), V.q_cap);
+        if (count == 0) continue;
+        int first = (int)((((int64_t)wave * PER_WAVE - before) % stride + stride) % stride);
+        for (; first < count; first += stride) {
+            const int idx = first + lane / G;
+            const bool has = idx < count;
+            const int p = has ? P.rayq[V.q_off + idx] : 0;
+            raycast_pixel<BACKWARD, G>(V.A, has ? p % V.A.W : V.A.W, has ? p / V.A.W : 0, V.tex, V.mip, V.depth,
+                                       V.hit, V.gdepth, V.gtex, s, INT_MAX, SurfaceArgs{0, false, nullptr, nullptr});
+        }
+        before += (count + PER_WAVE - 1) / PER_WAVE * PER_WAVE;
     }
 }
 
@@ -890,10 +941,14 @@ extern "C" hfr_status hfr_raycast_static(const hfr_camera* cam, const hfr_domain
     return hfr_ok();
 }
 
-hfr_status launch_raycast_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s)
+hfr_status launch_raycast_batch(const BatchDev& P, int blocks, int tail_blocks, bool backward, hipStream_t s)
 {
     if (backward) raycast_batch_kernel<true><<<dim3(blocks), dim3(256), 0, s>>>(P);
     else raycast_batch_kernel<false><<<dim3(blocks), dim3(256), 0, s>>>(P);
     HFR_LAUNCH_CHECK(backward ? "raycast_backward (batch)" : "raycast (batch)");
+    if (!P.ray_queue) return HFR_OK;
+    if (backward) raycast_batch_tail_kernel<true><<<dim3(tail_blocks), dim3(256), 0, s>>>(P);
+    else raycast_batch_tail_kernel<false><<<dim3(tail_blocks), dim3(256), 0, s>>>(P);
+    HFR_LAUNCH_CHECK(backward ? "raycast_backward long rays (batch)" : "raycast long rays (batch)");
     return HFR_OK;
 }

@@ -220,7 +220,9 @@ def test_backward_matches_oracle(gpu, batch):
 
 @pytest.mark.parametrize("tuning", [dict(disc_blocks_per_cu=1, ray_blocks_per_cu=1, ray_tile_w=64, disc_grain=1),
                                     dict(disc_blocks_per_cu=8, ray_blocks_per_cu=2, ray_tile_w=16, disc_grain=64),
-                                    dict(disc_blocks_per_cu=2, ray_blocks_per_cu=8, ray_tile_w=32, disc_grain=3)])
+                                    dict(disc_blocks_per_cu=2, ray_blocks_per_cu=8, ray_tile_w=32, disc_grain=3),
+                                    dict(disc_blocks_per_cu=4, ray_blocks_per_cu=4, ray_tile_w=8, disc_grain=8,
+                                         ray_queue=1)])
 def test_tuning_does_not_change_results(gpu, batch, tuning):
     R, cams, _ = batch
     R.set_tuning()
@@ -264,3 +266,67 @@ def test_graph_replays_follow_camera_changes(gpu, batch):
                 assert err <= 1e-5 and per.all(), (rep, err, per.mean())
         assert bool(gpu.isfinite(y))
     R.set_cameras(cams)
+
+
+def test_tuning_rejects_a_bad_queue_switch(gpu, batch):
+    from paper_2201_10887_amd._lib import HfrError
+    R = batch[0]
+    with pytest.raises(HfrError):
+        R.set_tuning(ray_queue=2)
+    R.set_tuning()
+
+
+@pytest.fixture(scope="module")
+def grazing(gpu, tiny_scene):
+    """Three views of the tiny terrain from 10 m above it, looking 1 degree down across it at
+    1024^2 cascades: rays near the horizon walk hundreds of cells, so many exceed the frame
+    kernel's 64-step budget and take the long-ray queue."""
+    from paper_2201_10887_amd.batch import BatchRenderer, Field, ViewSpec
+    s = tiny_scene
+    w = s.work
+    f0 = Field(s.leaves, w.side, w.max_depth, w.cutoff)
+    sizes = [(256, 128), (200, 100), (128, 64)]
+    specs = [ViewSpec(0, 2, 1024, W, H, 0.5, 0.05) for (W, H) in sizes]
+    R = BatchRenderer([f0], specs, backward=True)
+    n = s.dem.shape[0]
+    cams = []
+    for a, ((W, H), (fx, fy, yaw)) in enumerate(zip(sizes, [(0.1, 0.1, 0.8), (0.9, 0.15, -0.7), (0.5, 0.9, 3.1)])):
+        x, y = fx * w.side, fy * w.side
+        z = float(s.dem[min(int(fy * n), n - 1), min(int(fx * n), n - 1)]) + 10.0
+        cams.append(synth.Camera(pos=(x, y, z), yaw=yaw, pitch=math.radians(-1.0), vfov=math.radians(60.0),
+                                 width=W, height=H))
+    R.set_cameras(cams)
+    return R, cams
+
+
+def test_long_ray_queue_equals_the_single_lane_walk(gpu, grazing):
+    """ray_queue = 1 sends the long rays to the lane-group launch: depth and hit bit-identical to
+    the single-lane walk, leaf gradients equal up to the order of the atomic adds; the views
+    queue rays in both passes."""
+    R, cams = grazing
+    gen = gpu.Generator(device="cuda").manual_seed(5)
+    R.set_tuning()
+    R.forward()
+    for b in R.bufs:
+        d = b["depth"]
+        b["grad_depth"].copy_(gpu.where(gpu.isfinite(d), gpu.randn(d.shape, generator=gen, device="cuda"),
+                                        gpu.zeros_like(d)))
+    R.backward()
+    gpu.cuda.synchronize()
+    ref = [{k: R.bufs[v][k].clone() for k in ("depth", "hit")} for v in range(R.n_views)]
+    gv0, gs0 = R.fields[0].grad_v.clone(), R.fields[0].grad_sigma.clone()
+    R.set_tuning(ray_queue=1)
+    R.forward()
+    fwd_long = api.batch_long_rays(R.plan)
+    R.backward()
+    bwd_long = api.batch_long_rays(R.plan)
+    gpu.cuda.synchronize()
+    print(f"batch long-ray queue: {fwd_long.tolist()} rays queued forward, {bwd_long.tolist()} backward", flush=True)
+    assert fwd_long.sum() > 0 and bwd_long.sum() > 0
+    for v in range(R.n_views):
+        assert gpu.equal(gpu.nan_to_num(R.bufs[v]["depth"], nan=-1.0), gpu.nan_to_num(ref[v]["depth"], nan=-1.0)), v
+        assert gpu.equal(R.bufs[v]["hit"], ref[v]["hit"]), v
+    for got, want in ((R.fields[0].grad_v, gv0), (R.fields[0].grad_sigma, gs0)):
+        err, per = G.grad_close(got.cpu().numpy(), want.cpu().numpy())
+        assert err <= 1e-5 and per.mean() >= 0.999, (err, per.mean())
+    R.set_tuning()

@@ -95,3 +95,21 @@ def test_1080p_view_against_the_oracle(c5, view):
     nbad, n = G.compare_hits(depth, hit, ref, cam, dom, cs, otex, allow_rate=5e-5, what=f"batch view {view}",
                              height_tol=1e-5 * V)
     print(f"batch C5 view {view}: {nbad} hit mismatches of {n}", flush=True)
+
+
+def test_long_ray_queue_keeps_every_view(c5):
+    """The same batch with the long-ray queue (eager launches): every view's depth and hit images
+    bit-identical to the graph replay's single-lane walks."""
+    torch, R = c5["torch"], c5["R"]
+    ref = [(b["depth"].clone(), b["hit"].clone()) for b in R.bufs]
+    R.set_tuning(ray_queue=1)
+    R.forward()
+    long_rays = api.batch_long_rays(R.plan)
+    torch.cuda.synchronize()
+    print(f"batch C5 long-ray queue: {int(long_rays.sum())} rays queued over {int((long_rays > 0).sum())} views",
+          flush=True)
+    assert long_rays.sum() > 0
+    for v, (b, (d, h)) in enumerate(zip(R.bufs, ref)):
+        assert torch.equal(torch.nan_to_num(b["depth"], nan=-1.0), torch.nan_to_num(d, nan=-1.0)), v
+        assert torch.equal(b["hit"], h), v
+    R.set_tuning()
