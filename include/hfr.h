@@ -181,7 +181,9 @@ void hfr_quadtree_destroy(hfr_quadtree* q);
  * levels.  Host arrays x, y, c, sigma of n leaves.  Lists are sorted by
  * leaf index.  Output: a library-owned object freed with
  * hfr_neighbours_destroy.  EINVAL: off-lattice leaves, cutoff <= 0,
- * slack < 0, more than INT32_MAX entries.  Host only, multi-threaded. */
+ * slack < 0.  ECAPACITY: more than INT32_MAX entries, which the 32-bit
+ * offsets of hfr_neighbours_export cannot address (the device builder's
+ * offsets are 64-bit).  Host only, multi-threaded. */
 typedef struct hfr_neighbours hfr_neighbours;
 hfr_status hfr_build_neighbours(int64_t n, const float* x, const float* y, const float* c,
                                 const float* sigma, double x0, double y0, double side,

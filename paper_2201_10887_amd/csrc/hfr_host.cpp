@@ -301,7 +301,7 @@ extern "C" hfr_status hfr_build_neighbours(int64_t n, const float* x, const floa
         for (unsigned t = 0; t < T; ++t) total += (int64_t)part_idx[t].size();
         if (total > INT32_MAX) {
             delete nb;
-            return hfr_fail(HFR_EINVAL, "influence lists hold %lld entries, above INT32_MAX", (long long)total);
+            return hfr_fail(HFR_ECAPACITY, "influence lists hold %lld entries, above the INT32_MAX that the 32-bit offsets hold (hfr_build_neighbours_device has 64-bit offsets)", (long long)total);
         }
         nb->off.resize(n + 1);
         nb->idx.reserve(total);

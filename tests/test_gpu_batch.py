@@ -186,36 +186,54 @@ def test_backward_matches_per_view_sum(gpu, batch):
 def test_backward_matches_oracle(gpu, batch):
     """Field 1 (per-leaf sigma): the oracle's own forward and adjoint, summed over the field's views.
 
-    Each side differentiates its own forward pass: textures that agree within
-    the texel tolerance, ray roots on them, and v_s in the sigma term.  The
-    stated bound (norm-relative 1e-3) holds; per leaf, grazing hits (small
-    f'(t)) and nearly flat neighbourhoods (small v_j - v_s) amplify the
-    texture difference, so per-leaf agreement is asked of 98 % of the leaves.
-    With identical inputs each adjoint meets the per-leaf bound on 99.9 %
-    (the single-view parity tests), and the batch equals the sum of the
-    single-view adjoints (test_backward_matches_per_view_sum)."""
+    Each side differentiates its own forward pass (textures that agree within the texel
+    tolerance, ray roots on them, v_s in the sigma term).  As in the single-view end-to-end
+    gradient tests, the loss of field 1's views takes the pixels that hit the same cell on both
+    sides at 2 degrees or more to the oracle's patch (nearer grazing, dt/dh is ill conditioned):
+    the depth gradient is zeroed elsewhere on both sides.  Then the parity bar holds: norm within
+    1e-3, every leaf within 2e-4 of the largest gradient, the per-leaf rule on 99.9 % of the
+    leaves with a gradient.  The batch also equals the sum of the single-view adjoints
+    (test_backward_matches_per_view_sum)."""
+    import torch
     R, cams, info = batch
     R.forward()
     gds = _grad_depths(R, 13)
-    R.backward()
     gpu.cuda.synchronize()
     fi = 1
     f = R.fields[fi]
-    gv_ref, gs_ref = np.zeros(f.n), np.zeros(f.n)
+    refs = {}
     for v, cam in enumerate(cams):
-        spec = R.specs[v]
-        if spec.field != fi:
+        if R.specs[v].field != fi:
             continue
-        cas, field, _, ref = oracle_view(R, v, cam, info)
+        cas, field, otex, ref = oracle_view(R, v, cam, info)
+        hit = R.bufs[v]["hit"].cpu().numpy().ravel()
+        keep = (hit == ref["hit"]) & np.isfinite(ref["depth"]) & G.well_conditioned(ref, cas, otex)
+        gds[v] = np.where(keep.reshape(gds[v].shape), gds[v], 0.0).astype(np.float32)
+        R.bufs[v]["grad_depth"].copy_(torch.as_tensor(gds[v], device="cuda"))
+        refs[v] = (cas, field, ref, keep)
+        print(f"batch view {v}: loss over {int(keep.sum())} of {int(np.isfinite(ref['depth']).sum())} hit pixels",
+              flush=True)
+    R.backward()
+    gpu.cuda.synchronize()
+    gv_ref, gs_ref = np.zeros(f.n), np.zeros(f.n)
+    for v, (cas, field, ref, keep) in refs.items():
+        spec = R.specs[v]
         gd = gds[v].astype(np.float64).ravel() * np.isfinite(ref["depth"])
         gtex = adjoint.texel_gradients(ref, gd, spec.K, spec.N)
         a, b = adjoint.leaf_gradients(cas, field, f.dom, gtex)
         gv_ref += a
         gs_ref += b
-    for got, want, frac in ((f.grad_v, gv_ref, 0.98), (f.grad_sigma, gs_ref, 0.98)):
-        err, per = G.grad_close(got.cpu().numpy(), want)
+    for name, got, want in (("v", f.grad_v, gv_ref), ("sigma", f.grad_sigma, gs_ref)):
+        g = got.cpu().numpy().astype(np.float64)
+        err, per = G.grad_close(g, want)
+        some = (want != 0) | (g != 0)
+        frac = float(per[some].mean())
+        worst = np.abs(g - want).max() / np.abs(want).max()
+        print(f"batch field 1 d/d{name}: norm rel {err:.2e}, per-leaf rule on {frac:.5f} of {int(some.sum())} "
+              f"leaves, worst {worst:.2e}", flush=True)
         assert err <= 1e-3, err
-        assert per.mean() >= frac, per.mean()
+        assert worst <= 2e-4, worst
+        assert frac >= 0.999, frac
 
 
 @pytest.mark.parametrize("tuning", [dict(disc_blocks_per_cu=1, ray_blocks_per_cu=1, ray_tile_w=64, disc_grain=1),
