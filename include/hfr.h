@@ -537,9 +537,9 @@ typedef struct {
  * and returns a plan (*out).  Cameras must be set (hfr_batch_set_cameras)
  * before the first launch.  EINVAL: n_fields or n_views outside [1, 4096],
  * a view naming a missing field, K, N or image size out of range, NULL
- * buffers, or a total work count above 2^31.  EUNSUPPORTED: a field whose
- * basis is not HFR_BASIS_GAUSSIAN.  ENOMEM / EDEVICE: allocation failures.
- * Synchronous. */
+ * buffers, a total work count above 2^31, or an unknown basis.  Fields may
+ * use either basis (each block of a field evaluates that field's).  ENOMEM /
+ * EDEVICE: allocation failures.  Synchronous. */
 hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32_t n_fields, const hfr_batch_view* views,
                                  int32_t n_views, hfr_batch_plan** out);
 void hfr_batch_plan_destroy(hfr_batch_plan* plan);

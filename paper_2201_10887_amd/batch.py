@@ -20,10 +20,12 @@ from . import api
 
 class Field:
     def __init__(self, leaves: dict, side: float, max_depth: int, cutoff: float, x0: float = 0.0, y0: float = 0.0,
-                 device: str = "cuda", with_grads: bool = True):
+                 device: str = "cuda", with_grads: bool = True, basis="gaussian"):
         import torch
         index = api.build_level_index(leaves, side, max_depth, x0, y0)
         self.L = api.DeviceLeaves(leaves, index, side, max_depth, cutoff, x0, y0, device=device)
+        if basis not in ("gaussian", api.BASIS_GAUSSIAN):
+            self.L = self.L.with_basis(basis)
         api.pack_leaves(self.L)
         self.dom = _Dom(x0, y0, x0 + side, y0 + side, float(np.min(leaves["v"])), float(np.max(leaves["v"])))
         self.c_min = float(np.min(leaves["c"]))

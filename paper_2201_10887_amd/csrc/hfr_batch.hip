@@ -164,8 +164,6 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     std::vector<bool> field_bwd(n_fields);
     for (int f = 0; f < n_fields; ++f) {
         const hfr_batch_field& F = fields[f];
-        if (F.leaves.basis != HFR_BASIS_GAUSSIAN)
-            return hfr_fail(HFR_EUNSUPPORTED, "field %d: batched launches use the Gaussian basis only", f);
         hfr_status st = leaf_tables(&F.leaves, false, &tables[f]);
         if (st == HFR_OK) st = check_domain(&F.dom);
         if (st != HFR_OK) return hfr_fail(st, "field %d: %s", f, hfr_last_error());
@@ -221,7 +219,8 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     std::vector<BatchField> fd(n_fields);
     for (int f = 0; f < n_fields; ++f) {
         const hfr_batch_field& F = fields[f];
-        fd[f] = BatchField{tables[f], Dom2{F.dom.x0, F.dom.y0, F.dom.x1, F.dom.y1}, F.grad_v, F.grad_sigma};
+        fd[f] = BatchField{tables[f], Dom2{F.dom.x0, F.dom.y0, F.dom.x1, F.dom.y1}, F.grad_v, F.grad_sigma,
+                           F.leaves.basis};
     }
     q->tex_start.assign(n_tex + 1, 0);
     q->mip_start.assign(HFR_MIP_PASSES * (n_tex + 1), 0);
@@ -295,7 +294,8 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     }
     q->P = BatchDev{q->fields_d, q->tex_d, q->tex_start_d, q->mip_start_d, q->views_d, q->ray_start_d, q->queues_d,
                     q->rayq_d, q->rayq_count_d, (int)n_tex, n_views, q->tuning.ray_tile_w, q->tuning.disc_grain,
-                    q->tuning.ray_queue};
+                    q->tuning.ray_queue, 0};
+    for (int f = 0; f < n_fields; ++f) q->P.any_wendland |= fields[f].leaves.basis == HFR_BASIS_WENDLAND;
     // the long-ray launch: enough lane groups that a typical queue is taken in one round
     int64_t pixels = 0;
     for (int v = 0; v < n_views; ++v) pixels += (int64_t)views[v].width * views[v].height;

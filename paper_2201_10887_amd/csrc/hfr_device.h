@@ -163,6 +163,7 @@ struct BatchField {
     Dom2 D;
     float* gv;
     float* gs;
+    int basis;  // HFR_BASIS_GAUSSIAN or HFR_BASIS_WENDLAND
 };
 
 // One cascade of one view.
@@ -204,6 +205,7 @@ struct BatchDev {
     int n_tex, n_views, tile_w;
     int disc_grain;        // texel blocks per discretize queue access
     int ray_queue;         // 1: rays past the step budget go to the queue, then a lane-group launch
+    int any_wendland;      // some field uses HFR_BASIS_WENDLAND
 };
 
 // Read-only view of descriptor memory through the constant address space: the

@@ -686,7 +686,11 @@ __global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, C
 // an XCD then work on neighbouring tiles at once and share node-table rows and
 // leaf records in its L2.
 
-template <bool BACKWARD>
+// WENDLAND: some field of the batch uses Wendland's basis, so each block
+// takes its field's basis; without such a field only the Gaussian body is
+// compiled in (both bodies in one kernel need more registers than 7
+// workgroups per CU leave, and spill a few).
+template <bool BACKWARD, bool WENDLAND>
 __global__ __launch_bounds__(256, 7) void discretize_batch_kernel(BatchDev P)
 {
     __shared__ typename std::conditional<BACKWARD, DiscBwdShared, DiscShared>::type sh;
@@ -719,9 +723,19 @@ __global__ __launch_bounds__(256, 7) void discretize_batch_kernel(BatchDev P)
             const BatchField& F = as_constant(P.fields, it.field);
             const int local = w - item_lo;
             const int bx = local % it.gx, by = local / it.gx;
-            if constexpr (BACKWARD)
-                discretize_backward_block<HFR_BASIS_GAUSSIAN>(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs, sh);
-            else discretize_block<HFR_BASIS_GAUSSIAN>(F.T, it.C, F.D, bx, by, it.tex, it.mask, sh);
+            // the field's basis (wave-uniform: one field per block)
+            if constexpr (BACKWARD) {
+                if (WENDLAND && F.basis == HFR_BASIS_WENDLAND)
+                    discretize_backward_block<HFR_BASIS_WENDLAND>(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs,
+                                                                  sh);
+                else
+                    discretize_backward_block<HFR_BASIS_GAUSSIAN>(F.T, it.C, F.D, bx, by, it.tex, it.gtex, F.gv, F.gs,
+                                                                  sh);
+            } else {
+                if (WENDLAND && F.basis == HFR_BASIS_WENDLAND)
+                    discretize_block<HFR_BASIS_WENDLAND>(F.T, it.C, F.D, bx, by, it.tex, it.mask, sh);
+                else discretize_block<HFR_BASIS_GAUSSIAN>(F.T, it.C, F.D, bx, by, it.tex, it.mask, sh);
+            }
             __syncthreads();  // LDS is reused by the next block of the run
         }
     }
@@ -882,8 +896,14 @@ extern "C" hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_dom
 
 hfr_status launch_discretize_batch(const BatchDev& P, int blocks, bool backward, hipStream_t s)
 {
-    if (backward) discretize_batch_kernel<true><<<dim3(blocks), dim3(64 * WAVES), 0, s>>>(P);
-    else discretize_batch_kernel<false><<<dim3(blocks), dim3(64 * WAVES), 0, s>>>(P);
+    const dim3 grid(blocks), block(64 * WAVES);
+    if (P.any_wendland) {
+        if (backward) discretize_batch_kernel<true, true><<<grid, block, 0, s>>>(P);
+        else discretize_batch_kernel<false, true><<<grid, block, 0, s>>>(P);
+    } else {
+        if (backward) discretize_batch_kernel<true, false><<<grid, block, 0, s>>>(P);
+        else discretize_batch_kernel<false, false><<<grid, block, 0, s>>>(P);
+    }
     HFR_LAUNCH_CHECK(backward ? "discretize_backward (batch)" : "discretize (batch)");
     return HFR_OK;
 }
