@@ -483,7 +483,8 @@ def main():
         return R.forward(cam, None, depth, hit)
 
     tuned = R.tune_raycast(cam)
-    print(f"[bench] long-ray queue: forward {R.long_ray_queue}, adjoint {R.long_ray_queue_backward} {tuned}",
+    print(f"[bench] long-ray queue: forward {R.long_ray_queue} (split {R.ray_band_deg}), adjoint "
+          f"{R.long_ray_queue_backward} (split {R.ray_band_deg_backward}) {tuned}",
           file=sys.stderr, flush=True)
     _, _, cas = forward()
     torch.cuda.synchronize()
@@ -509,9 +510,11 @@ def main():
     stage = {
         "discretize": lambda: api.discretize(R.L, R.dom, cas, R.tex, R.mask),
         "build_maxmip": lambda: api.build_maxmip(R.tex, R.mip),
-        "raycast": lambda: api.raycast(cam, R.dom, cas, R.tex, R.mip, depth, hit, None, R.ray_work(cam)),
+        "raycast": lambda: api.raycast(cam, R.dom, cas, R.tex, R.mip, depth, hit, None, R.ray_work(cam),
+                                       R.ray_band_rows(cam)),
         "raycast_backward": lambda: api.raycast_backward(cam, R.dom, cas, R.tex, R.mip, grad_depth, gtex, None,
-                                                         R.ray_work(cam, backward=True)),
+                                                         R.ray_work(cam, backward=True),
+                                                         R.ray_band_rows(cam, backward=True)),
         "discretize_backward": lambda: api.discretize_backward(R.L, R.dom, cas, R.tex, gtex, gv, gs),
     }
     # the same frame's textures with the other basis (Wendland C2 on the same support)
@@ -597,7 +600,9 @@ def main():
         "fwd_bwd_ms": round(ms_train, 4),
         "fwd_bwd_over_fwd": round(ms_train / ms_fwd, 3),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "long_ray_queue": {"forward": R.long_ray_queue, "adjoint": R.long_ray_queue_backward, "tuning_ms": tuned},
+        "long_ray_queue": {"forward": R.long_ray_queue, "adjoint": R.long_ray_queue_backward,
+                           "split_deg_forward": R.ray_band_deg, "split_deg_adjoint": R.ray_band_deg_backward,
+                           "tuning_ms": tuned},
         "fit_cascades_host_us": round(fit_us, 1),
         "startup_ms": startup,
         "texel_reuse_flight": reuse,

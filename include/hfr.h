@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 11
+#define HFR_ABI_VERSION 12
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -369,11 +369,12 @@ hfr_status hfr_build_maxmip(const float* tex, int32_t K, int32_t N, float* mip, 
  * iteration cap (a status word the caller may read once the stream has
  * reached it; 0 on a correct walk).  With it, a ray still walking after a
  * fixed number of cell steps is queued there and finished by a second
- * kernel in which several lanes share it, each walking one consecutive piece
- * of its parameter range (the first hit is that of the earliest piece with
- * one): the few long rays that graze the surface near the horizon stop
- * setting the frame time.  Results agree with the NULL path up to FP64
- * rounding of the hit parameter.  Concurrent calls must not share work.
+ * kernel in which 16 lanes share it: each step tests the next 16 nodes of
+ * the current pyramid level along the ray at once, with the single-lane
+ * walk's arithmetic, so depth and hit agree with the NULL path's (equal on
+ * the benchmark frames); the few long rays that graze the surface near the
+ * horizon stop setting the frame time.
+ * Concurrent calls must not share work.
  * EINVAL: image size outside [1, 16384], K/N as above. */
 hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
                        int32_t K, const float* tex, const float* mip, float* depth, int32_t* hit,
@@ -391,6 +392,26 @@ hfr_status hfr_raycast_backward(const hfr_camera* cam, const hfr_domain* dom,
                                 const hfr_cascade* cas, int32_t K, const float* tex,
                                 const float* mip, const float* grad_depth, float* grad_tex,
                                 int32_t* work, hfr_stream stream);
+
+/* hfr_raycast and hfr_raycast_backward with the frame split at a row (not in
+ * the paper; a scheduling choice with the same outputs).  Rows 0 ..
+ * band_rows - 1, rounded up to a multiple of 16, are walked first with the
+ * long-ray queue in work (required); a second launch then walks the queued
+ * rays beside rows band_rows .. H - 1, whose rays each finish on their own
+ * lane.  Long rays graze the surface just below the horizon, so a band that
+ * ends a few degrees below it takes them all, and their lane-group walks run
+ * while the rest of the image is cast instead of after it.  band_rows >= H
+ * is hfr_raycast with a workspace; 0 walks every ray on its own lane.
+ * Depth and hit are hfr_raycast's (the adjoint's sums differ only in the
+ * order of the atomic adds).  EINVAL: band_rows < 0, work NULL, as for
+ * hfr_raycast otherwise. */
+hfr_status hfr_raycast_split(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                             int32_t K, const float* tex, const float* mip, float* depth, int32_t* hit,
+                             int32_t* work, int32_t band_rows, hfr_stream stream);
+hfr_status hfr_raycast_backward_split(const hfr_camera* cam, const hfr_domain* dom,
+                                      const hfr_cascade* cas, int32_t K, const float* tex,
+                                      const float* mip, const float* grad_depth, float* grad_tex,
+                                      int32_t* work, int32_t band_rows, hfr_stream stream);
 
 /* Several heightfields per frame (Section 2: the input is a terrain model and
  * relative water depths on the same adaptive grid; Table 1 times one

@@ -99,6 +99,8 @@ SIGNATURES = {
     "hfr_build_maxmip": ([P, I32, I32, P, P], I32),
     "hfr_raycast": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
     "hfr_raycast_backward": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, P], I32),
+    "hfr_raycast_split": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, I32, P], I32),
+    "hfr_raycast_backward_split": ([PP(Camera), PP(Domain), PP(Cascade), I32, P, P, P, P, P, I32, P], I32),
     "hfr_quadtree_device_workspace": ([I64, I32, PP(I64)], I32),
     "hfr_neighbours_device_workspace": ([I64, PP(I64)], I32),
     "hfr_build_neighbours_device": ([PP(Leaves), F32, P, P, PP(I64), P], I32),

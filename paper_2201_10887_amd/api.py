@@ -8,6 +8,7 @@ shapes and dtypes and converts structures.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Optional, Sequence
 
 import numpy as np
@@ -398,18 +399,35 @@ def _work_ptr(work, cam, device):
     return _dev(work, torch.int32, (cam.width * cam.height + 2,), "work")
 
 
-def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, stream=None, work=True):
+def raycast(cam, dom, cascades: ctypes.Array, tex, mip, depth=None, hit=None, stream=None, work=True,
+            band_rows=None):
+    """``hfr_raycast``; with ``band_rows`` (and a workspace) ``hfr_raycast_split``."""
     import torch
     K, N = len(cascades), cascades[0].n
     if depth is None:
         depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=tex.device)
     if hit is None:
         hit = torch.empty((cam.height, cam.width), dtype=torch.int32, device=tex.device)
-    call("hfr_raycast", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
-         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
-         _dev(depth, torch.float32, (cam.height, cam.width), "depth"),
-         _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _work_ptr(work, cam, tex.device), _stream(stream))
+    args = [ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+            _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
+            _dev(depth, torch.float32, (cam.height, cam.width), "depth"),
+            _dev(hit, torch.int32, (cam.height, cam.width), "hit"), _work_ptr(work, cam, tex.device)]
+    if band_rows is None:
+        call("hfr_raycast", *args, _stream(stream))
+    else:
+        call("hfr_raycast_split", *args, int(band_rows), _stream(stream))
     return depth, hit
+
+
+def band_rows(cam, degrees: float) -> int:
+    """Image rows whose central ray points at most ``degrees`` below the horizontal (the camera has no
+    roll, so a row's elevation is pitch + atan(s tan(vfov / 2)), s from 1 at the top to -1 at the bottom);
+    the band ``raycast(..., band_rows=)`` walks first."""
+    ty = math.tan(0.5 * cam.vfov)
+    a = min(max(-math.radians(degrees) - cam.pitch, -1.55), 1.55)
+    s = math.tan(a) / ty  # rows with s >= this are in the band
+    rows = int(math.floor(0.5 * cam.height * (1.0 - s)))
+    return min(max(rows, 0), cam.height)
 
 
 def raycast_static_max_pixels() -> int:
@@ -431,15 +449,20 @@ def raycast_static(cam, dom, cascades: ctypes.Array, tex, mip, depth, hit, strea
 
 
 def raycast_backward(cam, dom, cascades: ctypes.Array, tex, mip, grad_depth, grad_tex=None, stream=None,
-                     work=True):
+                     work=True, band_rows=None):
+    """``hfr_raycast_backward``; with ``band_rows`` (and a workspace) ``hfr_raycast_backward_split``."""
     import torch
     K, N = len(cascades), cascades[0].n
     if grad_tex is None:
         grad_tex = torch.zeros((K, N, N), dtype=torch.float32, device=tex.device)
-    call("hfr_raycast_backward", ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
-         _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
-         _dev(grad_depth, torch.float32, (cam.height, cam.width), "grad_depth"),
-         _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _work_ptr(work, cam, tex.device), _stream(stream))
+    args = [ctypes.byref(camera(cam)), ctypes.byref(domain(dom)), cascades, K,
+            _dev(tex, torch.float32, (K, N, N), "tex"), _dev(mip, torch.float32, (K, mip_size(N)), "mip"),
+            _dev(grad_depth, torch.float32, (cam.height, cam.width), "grad_depth"),
+            _dev(grad_tex, torch.float32, (K, N, N), "grad_tex"), _work_ptr(work, cam, tex.device)]
+    if band_rows is None:
+        call("hfr_raycast_backward", *args, _stream(stream))
+    else:
+        call("hfr_raycast_backward_split", *args, int(band_rows), _stream(stream))
     return grad_tex
 
 

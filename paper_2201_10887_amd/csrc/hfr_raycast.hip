@@ -589,9 +589,10 @@ template <bool BACKWARD, bool NEARER>
 __global__ __launch_bounds__(256, BACKWARD ? 4 : 6) void raycast_kernel(RayArgs A, const float* __restrict__ tex,
                                                       const float* __restrict__ mip, float* __restrict__ depth,
                                                       int32_t* __restrict__ hit, const float* __restrict__ gdepth,
-                                                      float* __restrict__ gtex, int* __restrict__ work, SurfaceArgs S)
+                                                      float* __restrict__ gtex, int* __restrict__ work, SurfaceArgs S,
+                                                      int row0)
 {
-    const int col = blockIdx.x * 16 + threadIdx.x, row = blockIdx.y * 16 + threadIdx.y;
+    const int col = blockIdx.x * 16 + threadIdx.x, row = row0 + blockIdx.y * 16 + threadIdx.y;
     const bool deferred = raycast_pixel<BACKWARD, 1, NEARER>(A, col, row, tex, mip, depth, hit, gdepth, gtex, 0,
                                                      work ? RAY_BUDGET : INT_MAX, S);
     if (!work) return;
@@ -635,6 +636,41 @@ __global__ __launch_bounds__(256) void raycast_tail_kernel(RayArgs A, const floa
 __global__ void zero_queue_kernel(int* __restrict__ work)
 {
     if (threadIdx.x < 2) work[threadIdx.x] = 0;  // queue length, rays stopped by the iteration cap
+}
+
+// The second launch of a split frame: workgroups [0, tail_blocks) walk the
+// queue that the first launch filled from the rows above rest_row0 (as
+// raycast_tail_kernel, over tail_blocks workgroups); the others walk rows
+// rest_row0 .. H - 1, one 16 x 16 tile each, every ray to its end on its own
+// lane.  The queued rays, which set the first launch's tail, then run beside
+// the bulk of the image instead of after it.  Lane l of a tile takes pixel
+// (l mod 16, l / 16) of it, as the frame kernel's 16 x 16 workgroup does.
+template <bool BACKWARD, bool NEARER>
+__global__ __launch_bounds__(256) void raycast_split_kernel(
+    RayArgs A, const float* __restrict__ tex, const float* __restrict__ mip, float* __restrict__ depth,
+    int32_t* __restrict__ hit, const float* __restrict__ gdepth, float* __restrict__ gtex, int* __restrict__ work,
+    SurfaceArgs S, int tail_blocks, int rest_row0)
+{
+    if ((int)blockIdx.x < tail_blocks) {
+        constexpr int G = RAY_SPLIT, PER_WAVE = 64 / G;
+        const int lane = __lane_id(), s = lane & (G - 1);
+        const int count = __builtin_amdgcn_readfirstlane(work[0]);
+        const int waves = tail_blocks * (int)(blockDim.x / 64);
+        const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+        for (int first = wave * PER_WAVE; first < count; first += waves * PER_WAVE) {
+            const int idx = first + lane / G;
+            const bool has = idx < count;
+            const int p = has ? work[2 + idx] : 0;
+            raycast_pixel<BACKWARD, G, NEARER>(A, has ? p % A.W : A.W, has ? p / A.W : 0, tex, mip, depth, hit, gdepth,
+                                               gtex, s, INT_MAX, S);
+        }
+        return;
+    }
+    const int b = (int)blockIdx.x - tail_blocks;
+    const int tiles_x = (A.W + 15) / 16;
+    const int tx = b % tiles_x, ty = b / tiles_x;
+    const int col = tx * 16 + (int)(threadIdx.x & 15), row = rest_row0 + ty * 16 + (int)(threadIdx.x >> 4);
+    raycast_pixel<BACKWARD, 1, NEARER>(A, col, row, tex, mip, depth, hit, gdepth, gtex, 0, INT_MAX, S);
 }
 
 // Persistent form over every view of a batch: each wave takes runs of
@@ -772,28 +808,52 @@ hfr_status ray_args(const hfr_camera* cam, const hfr_domain* dom, const hfr_casc
 
 namespace {
 
-// The frame kernel, then (with a workspace) the queue of long rays.
+// The frame kernel, then (with a workspace) the queue of long rays.  With
+// band_rows < H (a workspace given) the frame is split: the frame kernel
+// walks rows 0 .. band_rows - 1 (rounded up to whole 16-row tiles) and
+// queues their long rays; raycast_split_kernel then walks the queue beside
+// the remaining rows.
 template <bool BACKWARD>
 void launch_raycast(const RayArgs& A, const float* tex, const float* mip, float* depth, int32_t* hit,
-                    const float* gdepth, float* gtex, int32_t* work, const SurfaceArgs& S0, hipStream_t s)
+                    const float* gdepth, float* gtex, int32_t* work, const SurfaceArgs& S0, hipStream_t s,
+                    int band_rows = INT_MAX)
 {
     SurfaceArgs S = S0;
     S.limit_count = work ? work + 1 : nullptr;
     if (work) zero_queue_kernel<<<1, 64, 0, s>>>(work);
-    const dim3 grid((A.W + 15) / 16, (A.H + 15) / 16);
+    const int tiles_x = (A.W + 15) / 16, tiles_y = (A.H + 15) / 16;
+    const int band_tiles = work ? (int)std::min<int64_t>(tiles_y, (std::max(band_rows, 0) + 15LL) / 16) : tiles_y;
     // the nearer pass is its own instantiation: the plain walk keeps no clip depth in registers
     bool nearer = false;
     if constexpr (!BACKWARD) nearer = S.nearer;
-    if constexpr (!BACKWARD) {
-        if (nearer)
-            raycast_kernel<false, true><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
+    if (band_tiles > 0) {
+        const dim3 grid(tiles_x, band_tiles);
+        if constexpr (!BACKWARD) {
+            if (nearer)
+                raycast_kernel<false, true><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work,
+                                                                         S, 0);
+        }
+        if (!nearer)
+            raycast_kernel<BACKWARD, false><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work,
+                                                                         S, 0);
     }
-    if (!nearer)
-        raycast_kernel<BACKWARD, false><<<grid, dim3(16, 16), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex, work, S);
     if (!work) return;
     // persistent: enough lane groups that a typical queue is taken in one round
     const int64_t pixels = (int64_t)A.W * A.H;
     const int blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(64, pixels / 1024));
+    if (band_tiles < tiles_y) {
+        const int rest = tiles_x * (tiles_y - band_tiles);
+        const int rest_row0 = band_tiles * 16;
+        if constexpr (!BACKWARD) {
+            if (nearer)
+                raycast_split_kernel<false, true><<<dim3(blocks + rest), dim3(256), 0, s>>>(
+                    A, tex, mip, depth, hit, gdepth, gtex, work, S, blocks, rest_row0);
+        }
+        if (!nearer)
+            raycast_split_kernel<BACKWARD, false><<<dim3(blocks + rest), dim3(256), 0, s>>>(
+                A, tex, mip, depth, hit, gdepth, gtex, work, S, blocks, rest_row0);
+        return;
+    }
     if constexpr (!BACKWARD) {
         if (nearer)
             raycast_tail_kernel<false, true><<<dim3(blocks), dim3(256), 0, s>>>(A, tex, mip, depth, hit, gdepth, gtex,
@@ -817,6 +877,37 @@ extern "C" hfr_status hfr_raycast(const hfr_camera* cam, const hfr_domain* dom, 
     launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr, nullptr},
                           (hipStream_t)stream);
     HFR_LAUNCH_CHECK("raycast");
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_raycast_split(const hfr_camera* cam, const hfr_domain* dom, const hfr_cascade* cas,
+                                        int32_t K, const float* tex, const float* mip, float* depth, int32_t* hit,
+                                        int32_t* work, int32_t band_rows, hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && depth && hit && work, "NULL texture, mipmap, output or workspace");
+    HFR_REQUIRE(band_rows >= 0, "band_rows %d is negative", band_rows);
+    launch_raycast<false>(A, tex, mip, depth, hit, nullptr, nullptr, work, SurfaceArgs{0, false, nullptr, nullptr},
+                          (hipStream_t)stream, band_rows);
+    HFR_LAUNCH_CHECK("raycast_split");
+    return hfr_ok();
+}
+
+extern "C" hfr_status hfr_raycast_backward_split(const hfr_camera* cam, const hfr_domain* dom,
+                                                 const hfr_cascade* cas, int32_t K, const float* tex,
+                                                 const float* mip, const float* grad_depth, float* grad_tex,
+                                                 int32_t* work, int32_t band_rows, hfr_stream stream)
+{
+    RayArgs A;
+    hfr_status st = ray_args(cam, dom, cas, K, &A);
+    if (st != HFR_OK) return st;
+    HFR_REQUIRE(tex && mip && grad_depth && grad_tex && work, "NULL texture, mipmap, gradient or workspace");
+    HFR_REQUIRE(band_rows >= 0, "band_rows %d is negative", band_rows);
+    launch_raycast<true>(A, tex, mip, nullptr, nullptr, grad_depth, grad_tex, work,
+                         SurfaceArgs{0, false, nullptr, nullptr}, (hipStream_t)stream, band_rows);
+    HFR_LAUNCH_CHECK("raycast_backward_split");
     return hfr_ok();
 }
 

@@ -62,6 +62,10 @@ class Renderer:
         # on its own lane.  tune_raycast picks each by timing both on a camera.
         self.long_ray_queue = True
         self.long_ray_queue_backward = True
+        # with the queue: split the frame at the row this many degrees below the horizon (rows above it
+        # first, then their queued rays beside the rest); None: queue every row's long rays
+        self.ray_band_deg = None
+        self.ray_band_deg_backward = None
         self._work = {}
         self.extra = []  # further surfaces on the same cells (add_surface)
         # frame-to-frame texel reuse (set_texel_reuse): fixed-lattice cascades, a second texture set
@@ -86,11 +90,19 @@ class Renderer:
             self._work[key] = api.ray_workspace(cam, self.device)
         return self._work[key]
 
-    def tune_raycast(self, cam, reps: int = 5) -> dict:
-        """Time the ray cast and its adjoint with and without the long-ray queue on this camera's
-        frame and keep the faster of each.  The queue pays off when a few long rays set the frame
+    def ray_band_rows(self, cam, backward: bool = False):
+        """Rows walked before the queued long rays (None: no split), for this camera."""
+        deg = self.ray_band_deg_backward if backward else self.ray_band_deg
+        queue = self.long_ray_queue_backward if backward else self.long_ray_queue
+        return api.band_rows(cam, deg) if (queue and deg is not None) else None
+
+    def tune_raycast(self, cam, reps: int = 5, band_degrees=(3.0, 6.0, 12.0, 24.0)) -> dict:
+        """Time the ray cast and its adjoint on this camera's frame every way the library offers and
+        keep the fastest of each: each ray on its own lane, the long-ray queue after the whole frame,
+        or the frame split at a row ``band_degrees`` below the horizon (the rows above first, then
+        their queued rays beside the rest).  The queue pays off when a few long rays set the frame
         time; when the frame is throughput-bound, walking them after the rest costs more than it
-        saves.  Returns the median times (ms)."""
+        saves, and the split lets them run beside it.  Returns the median times (ms)."""
         import torch
         self.generation += 1
         cas = self.fit(cam)
@@ -117,13 +129,19 @@ class Renderer:
             return sorted(ts)[len(ts) // 2]
 
         res = {}
-        for name, wk in (("single_lane", None), ("queue", work)):
+        ways = [("single_lane", None, None), ("queue", work, None)]
+        ways += [(f"split_{d:g}deg", work, d) for d in band_degrees]
+        for name, wk, deg in ways:
+            band = None if deg is None else api.band_rows(cam, deg)
             res[f"raycast_{name}"] = median_ms(
-                lambda: api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, None, wk))
+                lambda: api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, None, wk, band))
             res[f"raycast_backward_{name}"] = median_ms(
-                lambda: api.raycast_backward(cam, self.dom, cas, self.tex, self.mip, gd, gtex, None, wk))
-        self.long_ray_queue = res["raycast_queue"] < res["raycast_single_lane"]
-        self.long_ray_queue_backward = res["raycast_backward_queue"] < res["raycast_backward_single_lane"]
+                lambda: api.raycast_backward(cam, self.dom, cas, self.tex, self.mip, gd, gtex, None, wk, band))
+        for prefix, attr_q, attr_d in (("raycast_", "long_ray_queue", "ray_band_deg"),
+                                       ("raycast_backward_", "long_ray_queue_backward", "ray_band_deg_backward")):
+            name, _, deg = min(ways, key=lambda w: res[prefix + w[0]])
+            setattr(self, attr_q, name != "single_lane")
+            setattr(self, attr_d, deg)
         self._work[(cam.width, cam.height)] = work
         return {k: round(v, 4) for k, v in res.items()}
 
@@ -202,7 +220,8 @@ class Renderer:
         if self.texel_reuse:
             self._prev_cas = cas
         work = self.ray_work(cam)
-        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream, work)
+        depth, hit = api.raycast(cam, self.dom, cas, self.tex, self.mip, depth, hit, stream, work,
+                                 self.ray_band_rows(cam) if work is not None else None)
         for s, surf in enumerate(self.extra, start=1):
             api.raycast_nearer(cam, self.dom, cas, surf["tex"], surf["mip"], s, depth, hit, stream, work)
         return depth, hit, cas
@@ -220,7 +239,8 @@ class Renderer:
             views = [(L, t, m) for (L, _, _), (t, m) in zip(views, surfaces)]
         if not self.extra:
             L, tex, mip = views[0]
-            api.raycast_backward(cam, self.dom, cascades, tex, mip, grad_depth, grad_tex, stream, work)
+            api.raycast_backward(cam, self.dom, cascades, tex, mip, grad_depth, grad_tex, stream, work,
+                                 self.ray_band_rows(cam, backward=True) if work is not None else None)
             api.discretize_backward(L, self.dom, cascades, tex, grad_tex, grad_v, grad_sigma, stream)
             return grad_v, grad_sigma
         if hit is None:

@@ -207,6 +207,37 @@ def test_long_ray_queue_matches_single_lane_walk(gpu, medium, standin):
     assert err <= 1e-5 and per.mean() >= 0.9999, (err, per.mean())
 
 
+@pytest.mark.parametrize("band", ["none", "3deg", "8deg", "half", "all"])
+def test_split_frame_matches_single_lane_walk(gpu, medium, standin, band):
+    """The frame split at a row (rows above it with the long-ray queue, then their queued rays beside
+    the rest): the single-lane walk's results, forward and adjoint, wherever the split falls."""
+    m = medium
+    cam = m["cam"]
+    rows = {"none": 0, "3deg": api.band_rows(cam, 3.0), "8deg": api.band_rows(cam, 8.0), "half": cam.height // 2,
+            "all": cam.height}[band]
+    tex = gpu.as_tensor(standin, device="cuda")
+    mip = api.build_maxmip(tex)
+    d0, h0 = api.raycast(cam, m["dom"], m["cas"], tex, mip, work=None)
+    work = api.ray_workspace(cam, "cuda")
+    d1, h1 = api.raycast(cam, m["dom"], m["cas"], tex, mip, work=work, band_rows=rows)
+    queued = int(work[0].item())
+    print(f"split at row {rows} of {cam.height}: {queued} rays queued", flush=True)
+    assert int(work[1].item()) == 0
+    if band in ("8deg", "half", "all"):
+        assert queued > 1000, queued  # the band holds the long rays
+    d0, d1, h0, h1 = (a.cpu().numpy() for a in (d0, d1, h0, h1))
+    fin = np.isfinite(d0)
+    assert np.array_equal(fin, np.isfinite(d1))
+    assert (h0 != h1).mean() <= 1e-5
+    assert np.max(np.abs(d0[fin] - d1[fin]) / np.abs(d0[fin])) <= 1e-6
+    rng = np.random.default_rng(13)
+    gd = gpu.as_tensor((rng.normal(0, 1, d0.shape) * fin).astype(np.float32), device="cuda")
+    g0 = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip, gd, work=None).cpu().numpy()
+    g1 = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip, gd, work=work, band_rows=rows).cpu().numpy()
+    err, per = G.grad_close(g1, g0)
+    assert err <= 1e-5 and per.mean() >= 0.9999, (err, per.mean())
+
+
 def test_backward_full_frame_sampled(gpu, medium, standin):
     m = medium
     cam = m["cam"]
