@@ -233,3 +233,53 @@ def test_raycast_backward_full_frame_sampled(gpu, large, standin):
                                  gpu.as_tensor(gd.reshape(cam.height, cam.width), device="cuda")).cpu().numpy()
     err, per = G.grad_close(g_gpu, g_ref)
     assert err <= 1e-3 and per.mean() >= 0.999, (err, per.mean())
+
+
+@pytest.fixture(scope="module")
+def library_tex(gpu, large):
+    """The 4K frame's own textures: the library's Eq. 2 over the 64.1M leaves (pinned to the oracle
+    within the texel tolerance by test_discretize_full_frame_sampled), as float32 on both sides."""
+    m = large
+    tex = api.discretize(m["L"], m["dom"], m["cas"])
+    return tex, tex.cpu().numpy()
+
+
+def test_raycast_on_library_textures_sampled(gpu, large, library_tex):
+    """The ray cast of the benchmark's 4K frame on its real, smooth Eq. 2 textures (not the raster
+    stand-in): the GPU (with the long-ray queue, as the benchmark runs it) and the FP64 oracle walk
+    the same float32 textures; 200k sampled pixels under the hit-cell and depth rules."""
+    m = large
+    cam = m["cam"]
+    tex, tex_h = library_tex
+    mip = api.build_maxmip(tex)
+    depth, hit = api.raycast(cam, m["dom"], m["cas"], tex, mip)
+    depth, hit = depth.cpu().numpy().ravel(), hit.cpu().numpy().ravel()
+    rng = np.random.default_rng(18)
+    pix = rng.choice(cam.width * cam.height, 200_000, replace=False)
+    _say("oracle ray cast of 200k pixels on the library textures")
+    ref = oray.raycast(cam, m["dom"], m["cs"], tex_h, cols=pix % cam.width, rows=pix // cam.width, threads=THREADS)
+    nbad, n = G.compare_hits(depth[pix], hit[pix], ref, cam, m["dom"], m["cs"], tex_h,
+                             what="large raycast on library textures")
+    _say(f"{nbad} hit mismatches of {n}")
+    assert np.isfinite(ref["depth"]).mean() > 0.3
+
+
+def test_raycast_backward_on_library_textures_sampled(gpu, large, library_tex):
+    m = large
+    cam = m["cam"]
+    K, N = len(m["cas"]), m["cas"][0].n
+    tex, tex_h = library_tex
+    mip = api.build_maxmip(tex)
+    rng = np.random.default_rng(20)
+    pix = rng.choice(cam.width * cam.height, 30_000, replace=False)
+    ref = oray.raycast(cam, m["dom"], m["cs"], tex_h, cols=pix % cam.width, rows=pix // cam.width,
+                       threads=THREADS)
+    g_pix = rng.normal(0, 1, len(pix)) * np.isfinite(ref["depth"])
+    gd = np.zeros(cam.width * cam.height, np.float32)
+    gd[pix] = g_pix
+    g_ref = adjoint.texel_gradients(ref, g_pix, K, N)
+    g_gpu = api.raycast_backward(cam, m["dom"], m["cas"], tex, mip,
+                                 gpu.as_tensor(gd.reshape(cam.height, cam.width), device="cuda")).cpu().numpy()
+    err, per = G.grad_close(g_gpu, g_ref)
+    _say(f"adjoint on library textures: norm rel {err:.2e}, per-entry rule on {per.mean():.6f}")
+    assert err <= 1e-3 and per.mean() >= 0.999, (err, per.mean())
