@@ -3,8 +3,8 @@
 // adjoint.  gfx950, wave64.
 //
 // Work decomposition.  A workgroup (4 waves) covers a 16 x 16 texel block of
-// one cascade (one launch per cascade, so the cascade polygon travels as a
-// kernel argument); each wave owns one 8 x 8 tile of the block.
+// one cascade; each wave owns one 8 x 8 tile of the block (4 x 16 or 16 x 4
+// where the cascade's texels are stretched along one axis).
 //  1. Visibility: the 17 cell rows touching the block get their polygon
 //     x-extent in LDS; every texel tests its incident cells; the block's
 //     16-bit halves of the visibility words are assembled with LDS atomics.
@@ -36,7 +36,6 @@
 namespace {
 
 constexpr int BS = 16;        // block side in texels
-constexpr int TS = 8;         // tile side in texels (one wave)
 constexpr int WAVES = 4;      // 2 x 2 tiles per block
 constexpr int BCAP = 512;     // candidate elements gathered per round (two per lane)
 constexpr int TCAP = 128;     // tile-list records per chunk
@@ -377,9 +376,10 @@ struct TileFrame {
     float npx, npy;        // minus the lane's texel centre relative to the block origin
 };
 
-__device__ inline TileFrame tile_frame(const TexCascade& C, const Dom2& D, const Rect& br, int ti0, int tj0, int i, int j)
+__device__ inline TileFrame tile_frame(const TexCascade& C, const Dom2& D, const Rect& br, int ti0, int tj0, int i, int j,
+                                       int tw, int th)
 {
-    const Rect tr = texel_rect(C, D, ti0, tj0, TS, TS);
+    const Rect tr = texel_rect(C, D, ti0, tj0, tw, th);
     TileFrame f;
     f.x0 = (float)(tr.x0 - br.x0);
     f.x1 = (float)(tr.x1 - br.x0);
@@ -419,8 +419,13 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int bi0 = bx * BS, bj0 = by * BS;
-    const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
-    const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
+    // A wave's tile: 8 x 8 texels, or 4 x 16 (16 x 4) when the cascade's texels are more than twice
+    // as wide as high (high as wide), so that the tile spans similar lengths on both axes and fewer
+    // records reach it (the far cascades' texels are stretched along the view).
+    const int lw = C.hx > 2.0 * C.hy ? 2 : (C.hy > 2.0 * C.hx ? 4 : 3);
+    const int tw = 1 << lw, th = 64 >> lw, per_row = BS >> lw;
+    const int ti0 = bi0 + (wave % per_row) * tw, tj0 = bj0 + (wave / per_row) * th;
+    const int i = ti0 + (lane & (tw - 1)), j = tj0 + (lane >> lw);
     const bool inside = i < N && j < N;
     const float Rf = level_radius(T);
     if (threadIdx.x == 0) any_vis = 0;
@@ -443,7 +448,7 @@ __device__ __forceinline__ void discretize_block(const Tables& T, const TexCasca
         }
     }
     const Rect br = texel_rect(C, D, bi0, bj0, BS, BS);
-    const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j);
+    const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j, tw, th);
     const bool tile_vis = __ballot(vis) != 0;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const float lim = T.T2 * 1.0001f, E = T.E;
@@ -567,8 +572,13 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     const int N = C.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int bi0 = bx * BS, bj0 = by * BS;
-    const int ti0 = bi0 + (wave & 1) * TS, tj0 = bj0 + (wave >> 1) * TS;
-    const int i = ti0 + (lane & (TS - 1)), j = tj0 + (lane >> 3);
+    // A wave's tile: 8 x 8 texels, or 4 x 16 (16 x 4) when the cascade's texels are more than twice
+    // as wide as high (high as wide), so that the tile spans similar lengths on both axes and fewer
+    // records reach it (the far cascades' texels are stretched along the view).
+    const int lw = C.hx > 2.0 * C.hy ? 2 : (C.hy > 2.0 * C.hx ? 4 : 3);
+    const int tw = 1 << lw, th = 64 >> lw, per_row = BS >> lw;
+    const int ti0 = bi0 + (wave % per_row) * tw, tj0 = bj0 + (wave / per_row) * th;
+    const int i = ti0 + (lane & (tw - 1)), j = tj0 + (lane >> lw);
     const bool inside = i < N && j < N;
     const float Rf = level_radius(T);
     float g = 0.0f, vs = 0.0f;
@@ -584,7 +594,7 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
     if (!any_act) return;
     const uint64_t active = __ballot(act);
     const Rect br = texel_rect(C, D, bi0, bj0, BS, BS);
-    const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j);
+    const TileFrame f = tile_frame(C, D, br, ti0, tj0, i, j, tw, th);
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const float lim = T.T2 * 1.0001f, E = T.E;
     unsigned short* tidx = sh.tidx_all[wave];
