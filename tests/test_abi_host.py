@@ -306,3 +306,25 @@ def test_batch_arguments_rejected_before_any_device_call():
     _raise_einval("hfr_batch_launch", None, None)
     _raise_einval("hfr_batch_launch_backward", None, None)
     _raise_einval("hfr_batch_cascades", None, 0, (api.Cascade * 1)())
+
+
+@pytest.mark.parametrize("pitch_deg, vfov_deg, height", [(-10.0, 60.0, 1080), (-3.0, 45.0, 720), (5.0, 70.0, 257),
+                                                        (-40.0, 30.0, 64)])
+@pytest.mark.parametrize("below", [3.0, 8.0, 24.0])
+def test_band_rows_follow_the_ray_elevations(pitch_deg, vfov_deg, height, below):
+    """api.band_rows (the split ray cast's band): every row above it has its central ray (the oracle's
+    camera model) at most `below` degrees under the horizontal, every row from it on more, to within
+    the half-row the pixel centres leave."""
+    import dataclasses
+    from oracle import camera as ocam
+    from paper_2201_10887_amd import synth
+    cam = synth.Camera(pos=(0.0, 0.0, 100.0), yaw=0.7, pitch=math.radians(pitch_deg), vfov=math.radians(vfov_deg),
+                       width=16, height=height)
+    rows = api.band_rows(cam, below)
+    assert 0 <= rows <= height
+    d = ocam.ray_directions(cam, np.full(height, 7.5), np.arange(height, dtype=np.float64))
+    # the central column of a 16-wide image: sample between columns 7 and 8 (the image's centre line)
+    elev = np.degrees(np.arcsin(d[:, 2] / np.linalg.norm(d, axis=1)))
+    slack = 0.5 * vfov_deg / height * 2.0  # one row's angle, generously
+    assert np.all(elev[:rows] >= -below - slack)
+    assert np.all(elev[rows:] <= -below + slack)
