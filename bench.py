@@ -25,12 +25,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 DISC_CASCADES_PER_LAUNCH = 4  # cascades of one view per discretize launch
+VALU_CLOCK_HZ = 2.4e9  # MI355X peak engine clock
 
 
-def recorded_traffic(kernel_source: str, summary: str):
-    """HBM bytes per launch from a committed counter summary (FETCH_SIZE and
-    WRITE_SIZE, each scaled by what the counter reads for a copy of known
-    size).  The figure is only valid for the kernel source it was taken on,
+def recorded_figure(kernel_source: str, summary: str, key: str):
+    """A per-launch figure from a committed counter summary (`key`: e.g. traffic_bytes_per_launch,
+    FETCH_SIZE and WRITE_SIZE each scaled by what the counter reads for a copy of known size, or
+    valu_instructions_per_launch).  The figure is only valid for the kernel source it was taken on,
     so it is returned only when the summary's recorded SHA-256 matches."""
     try:
         with open(os.path.join(ROOT, summary)) as f:
@@ -41,12 +42,17 @@ def recorded_traffic(kernel_source: str, summary: str):
         return None
     fields = {}
     for line in text.splitlines():
-        if ":" in line and line.lstrip("- `").split(":")[0] in ("source_sha256", "traffic_bytes_per_launch"):
+        if ":" in line and line.lstrip("- `").split(":")[0] in ("source_sha256", key):
             k, v = line.lstrip("- `").split(":", 1)
             fields[k] = v.strip().strip("`")
-    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != sha or key not in fields:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(float(fields[key]))
+
+
+def recorded_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch recorded with the counters (see recorded_figure)."""
+    return recorded_figure(kernel_source, summary, "traffic_bytes_per_launch")
 
 
 def build_scene(name: str):
@@ -574,6 +580,14 @@ def main():
         traffic = recorded_traffic("paper_2201_10887_amd/csrc/hfr_discretize.hip",
                                    "profiles/discretize_kernel_medium_hbm_counters.md")
     launches = -(-K // DISC_CASCADES_PER_LAUNCH)  # the library discretizes up to four cascades per launch
+    # VALU issue: a CU issues at most one wave64 VALU instruction per cycle (four SIMDs, four cycles each)
+    valu = recorded_figure("paper_2201_10887_amd/csrc/hfr_discretize.hip",
+                           "profiles/discretize_kernel_medium_valu_counters.md",
+                           "valu_instructions_per_launch") if args.workload == "medium" else None
+    if valu is not None:
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        roof["valu_instructions_per_launch"] = valu
+        roof["valu_issue_frac"] = round(valu / (cus * VALU_CLOCK_HZ) / (stage_ms["discretize"] / launches * 1e-3), 4)
     roof.update({"traffic": traffic, "kernel": "discretize_kernel<0>", "launches": launches,
                  "per_launch_ms": round(stage_ms["discretize"] / launches, 4),
                  "algorithmic_flops_per_launch": round(work["flops"] / launches), "algorithmic_bytes_per_launch":
