@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HFR_ABI_VERSION 12
+#define HFR_ABI_VERSION 13
 #define HFR_MAX_POLY 32
 #define HFR_MAX_CASCADES 8
 #define HFR_MAX_TEX_N 8192
@@ -538,20 +538,27 @@ typedef struct {
  * workgroups (256 threads) per compute unit for the discretize kernels and
  * the ray-cast kernels, in [1, 16].  ray_tile_w: width of the 64-pixel tile
  * a wave takes at a time (8, 16, 32 or 64; height 64 / ray_tile_w).
- * disc_grain: 16 x 16 texel blocks a discretize workgroup takes per queue
- * access, in [1, 64] (small runs keep the blocks running at once close
- * together, large runs need fewer atomics).  ray_queue: 1 = hfr_raycast's
+ * disc_grain: the most 16 x 16 texel blocks a discretize workgroup takes
+ * per queue access, in [1, 64] (a share of what is left in its chunk of the
+ * work, at most this many: small runs keep the blocks running at once close
+ * together and the finish even, large runs need fewer atomics).  ray_queue: 1 = hfr_raycast's
  * long-ray queue for the batch (a ray still walking after 64 steps is queued
  * and finished by a second launch with 16 lanes per ray; the plan holds room
  * for a quarter of each view's pixels and a ray past that finishes in the
  * first launch), 0 = every ray finishes in the first launch; outputs are the
- * same either way.  Defaults: 4, 4, 32, 8, 0. */
+ * same either way.  ray_grain: the most 64-pixel tiles a ray-cast wave takes
+ * per queue access, in [1, 32] (a wave takes a share of what is left in its
+ * chunk of the work, at most this many: a small cap keeps one wave from
+ * being left with a long run of expensive tiles, such as a view's horizon
+ * rows, after the others are done; a large one needs fewer atomics).
+ * Defaults: 4, 4, 32, 8, 0, 8. */
 typedef struct {
     int32_t disc_blocks_per_cu;
     int32_t ray_blocks_per_cu;
     int32_t ray_tile_w;
     int32_t disc_grain;
     int32_t ray_queue;
+    int32_t ray_grain;
 } hfr_batch_tuning;
 
 /* Validates the fields and views, copies their descriptors to device memory

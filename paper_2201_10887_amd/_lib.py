@@ -68,7 +68,8 @@ class BatchView(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("disc_blocks_per_cu", ctypes.c_int32), ("ray_blocks_per_cu", ctypes.c_int32),
-                ("ray_tile_w", ctypes.c_int32), ("disc_grain", ctypes.c_int32), ("ray_queue", ctypes.c_int32)]
+                ("ray_tile_w", ctypes.c_int32), ("disc_grain", ctypes.c_int32), ("ray_queue", ctypes.c_int32),
+                ("ray_grain", ctypes.c_int32)]
 
 
 P = ctypes.c_void_p

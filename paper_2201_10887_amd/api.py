@@ -564,9 +564,9 @@ def batch_plan_destroy(plan: BatchPlan) -> None:
 
 
 def batch_set_tuning(plan: BatchPlan, disc_blocks_per_cu: int = 4, ray_blocks_per_cu: int = 4,
-                     ray_tile_w: int = 32, disc_grain: int = 8, ray_queue: int = 0) -> None:
+                     ray_tile_w: int = 32, disc_grain: int = 8, ray_queue: int = 0, ray_grain: int = 8) -> None:
     t = _lib.BatchTuning(int(disc_blocks_per_cu), int(ray_blocks_per_cu), int(ray_tile_w), int(disc_grain),
-                         int(ray_queue))
+                         int(ray_queue), int(ray_grain))
     call("hfr_batch_set_tuning", plan.handle, ctypes.byref(t))
 
 

@@ -25,10 +25,11 @@ DEFAULT_CACHE = os.path.join(HERE, "_build", "autotune.json")
 
 DEFAULT_GRID = {
     "disc_blocks_per_cu": (4, 7),
-    "disc_grain": (4, 8, 16),
+    "disc_grain": (8, 16),
     "ray_blocks_per_cu": (2, 4),
-    "ray_tile_w": (8, 16, 32),
+    "ray_tile_w": (16, 32),
     "ray_queue": (0, 1),
+    "ray_grain": (4, 8, 16),
 }
 
 

@@ -77,7 +77,8 @@ class BatchRenderer:
             d.update(b)
             vdesc.append(d)
         self.plan = api.batch_plan_create(fdesc, vdesc)
-        self.tuning = dict(disc_blocks_per_cu=4, ray_blocks_per_cu=4, ray_tile_w=32, disc_grain=8, ray_queue=0)
+        self.tuning = dict(disc_blocks_per_cu=4, ray_blocks_per_cu=4, ray_tile_w=32, disc_grain=8, ray_queue=0,
+                           ray_grain=8)
         if tuning:
             self.set_tuning(**tuning)
 
@@ -86,10 +87,11 @@ class BatchRenderer:
         return len(self.specs)
 
     def set_tuning(self, disc_blocks_per_cu: int = 4, ray_blocks_per_cu: int = 4, ray_tile_w: int = 32,
-                   disc_grain: int = 8, ray_queue: int = 0):
-        api.batch_set_tuning(self.plan, disc_blocks_per_cu, ray_blocks_per_cu, ray_tile_w, disc_grain, ray_queue)
+                   disc_grain: int = 8, ray_queue: int = 0, ray_grain: int = 8):
+        api.batch_set_tuning(self.plan, disc_blocks_per_cu, ray_blocks_per_cu, ray_tile_w, disc_grain, ray_queue,
+                             ray_grain)
         self.tuning = dict(disc_blocks_per_cu=disc_blocks_per_cu, ray_blocks_per_cu=ray_blocks_per_cu,
-                           ray_tile_w=ray_tile_w, disc_grain=disc_grain, ray_queue=ray_queue)
+                           ray_tile_w=ray_tile_w, disc_grain=disc_grain, ray_queue=ray_queue, ray_grain=ray_grain)
 
     def set_cameras(self, cams: Sequence, stream=None):
         api.batch_set_cameras(self.plan, cams, stream)

@@ -73,6 +73,7 @@ hfr_status check_tuning(const hfr_batch_tuning& t)
                 "ray_tile_w %d is not 8, 16, 32 or 64", t.ray_tile_w);
     HFR_REQUIRE(t.disc_grain >= 1 && t.disc_grain <= 64, "disc_grain %d outside [1, 64]", t.disc_grain);
     HFR_REQUIRE(t.ray_queue == 0 || t.ray_queue == 1, "ray_queue %d is not 0 or 1", t.ray_queue);
+    HFR_REQUIRE(t.ray_grain >= 1 && t.ray_grain <= 32, "ray_grain %d outside [1, 32]", t.ray_grain);
     return HFR_OK;
 }
 
@@ -88,7 +89,7 @@ struct hfr_batch_plan {
     std::vector<hfr_cascade> cas;   // from the last hfr_batch_set_cameras
     std::vector<int> tex_start, mip_start, ray_start;
     int pass_blocks[HFR_MIP_PASSES] = {};
-    hfr_batch_tuning tuning{4, 4, 32, 8, 0};
+    hfr_batch_tuning tuning{4, 4, 32, 8, 0, 8};
     int tail_blocks = 64;            // workgroups of the long-ray launch
     bool cameras_set = false, backward_ok = false, upload_pending = false;
     // pinned staging of the per-camera descriptors
@@ -294,7 +295,7 @@ extern "C" hfr_status hfr_batch_plan_create(const hfr_batch_field* fields, int32
     }
     q->P = BatchDev{q->fields_d, q->tex_d, q->tex_start_d, q->mip_start_d, q->views_d, q->ray_start_d, q->queues_d,
                     q->rayq_d, q->rayq_count_d, (int)n_tex, n_views, q->tuning.ray_tile_w, q->tuning.disc_grain,
-                    q->tuning.ray_queue, 0};
+                    q->tuning.ray_queue, q->tuning.ray_grain, 0};
     for (int f = 0; f < n_fields; ++f) q->P.any_wendland |= fields[f].leaves.basis == HFR_BASIS_WENDLAND;
     // the long-ray launch: enough lane groups that a typical queue is taken in one round
     int64_t pixels = 0;
@@ -335,6 +336,7 @@ extern "C" hfr_status hfr_batch_set_tuning(hfr_batch_plan* plan, const hfr_batch
     plan->P.tile_w = tuning->ray_tile_w;
     plan->P.disc_grain = tuning->disc_grain;
     plan->P.ray_queue = tuning->ray_queue;
+    plan->P.ray_grain = tuning->ray_grain;
     return hfr_ok();
 }
 
@@ -398,7 +400,7 @@ extern "C" hfr_status hfr_batch_launch(const hfr_batch_plan* plan, hfr_stream st
     HFR_REQUIRE(plan != nullptr, "plan is NULL");
     HFR_REQUIRE(plan->cameras_set, "no cameras set");
     hipStream_t s = (hipStream_t)stream;
-    zero_ints_kernel<<<1, 64, 0, s>>>(plan->queues_d, HFR_QUEUE_WORDS);
+    zero_ints_kernel<<<(HFR_QUEUE_WORDS + 255) / 256, 256, 0, s>>>(plan->queues_d, HFR_QUEUE_WORDS);
     HFR_LAUNCH_CHECK("batch queue reset");
     if (plan->P.ray_queue) {
         const int nv = plan->P.n_views;
@@ -419,7 +421,7 @@ extern "C" hfr_status hfr_batch_launch_backward(const hfr_batch_plan* plan, hfr_
     HFR_REQUIRE(plan->backward_ok, "the plan has no backward pass (a view lacks grad_depth / grad_tex, or a field "
                                    "lacks grad_v / grad_sigma / sigma)");
     hipStream_t s = (hipStream_t)stream;
-    zero_ints_kernel<<<1, 64, 0, s>>>(plan->queues_d, HFR_QUEUE_WORDS);
+    zero_ints_kernel<<<(HFR_QUEUE_WORDS + 255) / 256, 256, 0, s>>>(plan->queues_d, HFR_QUEUE_WORDS);
     HFR_LAUNCH_CHECK("batch queue reset");
     const int nf = (int)plan->fields.size();
     zero_grads_kernel<<<dim3(64, plan->P.n_tex + nf), dim3(256), 0, s>>>(plan->P, nf);

@@ -188,8 +188,15 @@ struct BatchView {
     int q_off, q_cap;  // the view's slice of the plan's long-ray queue (pixel indices)
 };
 
-constexpr int HFR_QUEUE_DISC = 0, HFR_QUEUE_RAY = 8, HFR_QUEUE_RAY_BWD = 16, HFR_QUEUE_DISC_BWD = 24;
-constexpr int HFR_QUEUE_WORDS = 32;
+// Work queues of the persistent batch launches: each splits its index range
+// into HFR_CHUNKS chunks (eight per XCD) with one counter per chunk, each
+// counter on its own 128-byte line.
+constexpr int HFR_CHUNKS = 64;
+constexpr int HFR_CHUNK_STRIDE = 32;  // ints between two chunk counters
+constexpr int HFR_QUEUE_SPAN = HFR_CHUNKS * HFR_CHUNK_STRIDE;
+constexpr int HFR_QUEUE_DISC = 0, HFR_QUEUE_DISC_BWD = HFR_QUEUE_SPAN, HFR_QUEUE_RAY = 2 * HFR_QUEUE_SPAN,
+              HFR_QUEUE_RAY_BWD = 3 * HFR_QUEUE_SPAN;
+constexpr int HFR_QUEUE_WORDS = 4 * HFR_QUEUE_SPAN;
 constexpr int HFR_MIP_PASSES = 2;  // 64 x 64-cell tiles to level 6, then one workgroup per cascade to the top
 
 struct BatchDev {
@@ -205,6 +212,7 @@ struct BatchDev {
     int n_tex, n_views, tile_w;
     int disc_grain;        // texel blocks per discretize queue access
     int ray_queue;         // 1: rays past the step budget go to the queue, then a lane-group launch
+    int ray_grain;         // most pixel tiles per ray-cast queue access
     int any_wendland;      // some field uses HFR_BASIS_WENDLAND
 };
 
@@ -222,35 +230,55 @@ hfr_status launch_discretize_batch(const BatchDev& P, int blocks, bool backward,
 hfr_status launch_maxmip_batch(const BatchDev& P, const int* pass_blocks, hipStream_t s);
 hfr_status launch_raycast_batch(const BatchDev& P, int blocks, int tail_blocks, bool backward, hipStream_t s);
 
-// Next range of work indices from a set of 8 queues that split [0, total)
-// into 8 contiguous chunks, one per XCD (the hardware deals workgroups to
-// the XCDs round-robin, so blockIdx.x & 7 names the workgroup's XCD; a
-// wrong guess only costs locality).  A caller starts with its own chunk and
-// moves to the next ones when it is exhausted.  Guided self-scheduling: a
-// grab takes a share of what is left in the chunk, remaining / (2 consumers),
-// clamped to [min_grain, max_grain], so early grabs are large (few atomics)
-// and the last ones small (an even finish); `consumers` is the number of
-// callers per XCD.  [*w0, *w1) is the range taken; false when all queues are
-// exhausted.  Each counter only grows, so every caller ends after at most 8
-// failed attempts.
-__device__ inline bool queue_grab(int* q, int total, int xcd, int min_grain, int max_grain, int consumers, int* w0,
-                                  int* w1)
+// Next range of work indices from nq <= 64 queues that split [0, total) into
+// nq contiguous chunks, their counters HFR_CHUNK_STRIDE ints apart; called by
+// a whole wave (every lane active), the result wave-uniform.  Guided
+// self-scheduling: a grab takes a share of what is left in the chunk,
+// remaining / (2 consumers), clamped to [min_grain, max_grain], so early
+// grabs are large (few atomics) and the last ones small (an even finish);
+// `consumers` is the number of callers per chunk.  A caller starts with its
+// home chunk (the hardware deals workgroups to the XCDs round-robin, so
+// blockIdx.x & 7 names the workgroup's XCD and the callers pick a home among
+// that XCD's chunks: neighbouring work shares an L2; a wrong guess only costs
+// locality).  Once the home chunk is exhausted (*scan, false at the first
+// call, records it), lane l looks at chunk (home + l) % nq and the wave takes
+// from the first one after its home chunk (in that order) with work left.
+// Many counters, each on its own cache line, spread the atomics, so the runs
+// can stay short without the atomics serialising.  [*w0, *w1) is the range
+// taken; false when every chunk is exhausted.  Each counter only grows and a
+// failed grab leaves its chunk exhausted, so the loop ends after at most
+// nq + 1 failed grabs.
+__device__ inline bool queue_grab_wave(int* q, int nq, int total, int home, int min_grain, int max_grain,
+                                       int consumers, bool* scan, int* w0, int* w1)
 {
-    for (int a = 0; a < 8; ++a) {
-        const int c = (xcd + a) & 7;
-        const int lo = (int)((int64_t)total * c / 8), hi = (int)((int64_t)total * (c + 1) / 8);
-        const int taken = __hip_atomic_load(&q[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int left = hi - lo - taken;
-        if (left <= 0) continue;
-        const int grain = min(max(left / (2 * consumers), min_grain), max_grain);
-        const int idx = lo + atomicAdd(&q[c], grain);
-        if (idx < hi) {
+    const int lane = __lane_id();
+    for (;;) {
+        const int c = (home + (*scan ? lane : 0)) % nq;
+        const int lo = (int)((int64_t)total * c / nq), hi = (int)((int64_t)total * (c + 1) / nq);
+        int left = 0;
+        if (*scan ? lane < nq : lane == 0)
+            left = hi - lo - __hip_atomic_load(&q[c * HFR_CHUNK_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t m = __ballot(left > 0);
+        if (m == 0) {
+            if (*scan) return false;
+            *scan = true;
+            continue;
+        }
+        const int pick = __ffsll((unsigned long long)m) - 1;
+        int idx = 0, end = 0;
+        if (lane == pick) {
+            const int grain = min(max(left / (2 * consumers), min_grain), max_grain);
+            idx = lo + atomicAdd(&q[c * HFR_CHUNK_STRIDE], grain);
+            end = min(idx + grain, hi);
+        }
+        idx = __shfl(idx, pick);
+        end = __shfl(end, pick);
+        if (idx < end) {
             *w0 = idx;
-            *w1 = min(idx + grain, hi);
+            *w1 = end;
             return true;
         }
     }
-    return false;
 }
 
 // Item holding work index w: the i with start[i] <= w < start[i + 1]

@@ -690,10 +690,11 @@ __global__ __launch_bounds__(256, 8) void discretize_backward_kernel(Tables T, C
 }
 
 // Persistent form over every cascade of every view of a batch: each
-// workgroup takes runs of P.disc_grain 16 x 16 texel blocks from the queues
-// until all are done; the cascade a block belongs to is found by one search
-// per run and followed forward inside it.  The runs stay short: the blocks of
-// an XCD then work on neighbouring tiles at once and share node-table rows and
+// workgroup takes runs of 16 x 16 texel blocks (guided, at most P.disc_grain)
+// from HFR_CHUNKS queues, eight per XCD, until all are done; wave 0 grabs for
+// the workgroup.  The cascade a block belongs to is found by one search per
+// run and followed forward inside it.  The runs stay short: the blocks of an
+// XCD then work on neighbouring tiles at once and share node-table rows and
 // leaf records in its L2.
 
 // WENDLAND: some field of the batch uses Wendland's basis, so each block
@@ -707,15 +708,21 @@ __global__ __launch_bounds__(256, 7) void discretize_batch_kernel(BatchDev P)
     __shared__ int work[3];
     int* q = P.queues + (BACKWARD ? HFR_QUEUE_DISC_BWD : HFR_QUEUE_DISC);
     const int total = P.tex_start[P.n_tex];
-    const int xcd = blockIdx.x & 7;
+    // home chunk: the workgroup's XCD (blockIdx.x & 7), then one of its eight
+    // chunks by the workgroup's slot on that XCD
+    const int home = (int)(blockIdx.x & 7) * 8 + (int)((blockIdx.x >> 3) & 7);
+    const int consumers = max(1, (int)gridDim.x / HFR_CHUNKS);
+    bool scan = false;
     for (;;) {
         __syncthreads();  // the previous run's LDS reads are done
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 64) {  // wave 0, every lane active
             int w0 = -1, w1 = -1;
-            const bool got = queue_grab(q, total, xcd, P.disc_grain, P.disc_grain, 1, &w0, &w1);
-            work[0] = got ? w0 : -1;
-            work[1] = w1;
-            work[2] = got ? find_item(P.tex_start, P.n_tex, w0) : 0;
+            const bool got = queue_grab_wave(q, HFR_CHUNKS, total, home, 1, P.disc_grain, consumers, &scan, &w0, &w1);
+            if (threadIdx.x == 0) {
+                work[0] = got ? w0 : -1;
+                work[1] = w1;
+                work[2] = got ? find_item(P.tex_start, P.n_tex, w0) : 0;
+            }
         }
         __syncthreads();
         const int w0 = __builtin_amdgcn_readfirstlane(work[0]);

@@ -674,8 +674,9 @@ __global__ __launch_bounds__(256) void raycast_split_kernel(
 }
 
 // Persistent form over every view of a batch: each wave takes runs of
-// 64-pixel tiles (tile_w x 64 / tile_w; guided: up to 32 early, down to 1 at
-// the end) from the queues until all are done; waves never wait for each other.
+// 64-pixel tiles (tile_w x 64 / tile_w; guided: up to P.ray_grain early, down
+// to 1 at the end) from HFR_CHUNKS queues, eight per XCD, until all are
+// done; waves never wait for each other.
 // With P.ray_queue a pixel whose walk exceeds RAY_BUDGET steps goes to its
 // view's slice of the long-ray queue (one reservation per wave and tile, as
 // in the frame kernel); a pixel that finds the slice full is walked again to
@@ -687,17 +688,21 @@ __global__ __launch_bounds__(256) void raycast_batch_kernel(BatchDev P)
 {
     int* q = P.queues + (BACKWARD ? HFR_QUEUE_RAY_BWD : HFR_QUEUE_RAY);
     const int total = P.ray_start[P.n_views];
-    const int xcd = blockIdx.x & 7;
     const int lane = __lane_id();
     const int tw = P.tile_w, th = 64 / tw;
+    // home chunk: the workgroup's XCD (blockIdx.x & 7), then one of its eight
+    // chunks by the wave's slot on that XCD
+    const int home = (int)(blockIdx.x & 7) * 8 + (int)(((blockIdx.x >> 3) * (blockDim.x / 64) + threadIdx.x / 64) & 7);
+    const int consumers = max(1, (int)(gridDim.x * (blockDim.x / 64)) / HFR_CHUNKS);
+    bool scan = false;
     for (;;) {
         int w0 = -1, w1 = -1, v = 0;
-        if (lane == 0 && queue_grab(q, total, xcd, 1, 32, max(1, (int)gridDim.x / 2), &w0, &w1))
-            v = find_item(P.ray_start, P.n_views, w0);
-        // every lane is active here, so the first active lane is lane 0: the
-        // values become wave-uniform (scalar registers, scalar descriptor loads)
+        // every lane is active here: the grab is wave-wide, its result uniform
+        if (!queue_grab_wave(q, HFR_CHUNKS, total, home, 1, P.ray_grain, consumers, &scan, &w0, &w1)) break;
+        if (lane == 0) v = find_item(P.ray_start, P.n_views, w0);
+        // the first active lane is lane 0: the values become wave-uniform
+        // (scalar registers, scalar descriptor loads)
         w0 = __builtin_amdgcn_readfirstlane(w0);
-        if (w0 < 0) break;
         w1 = __builtin_amdgcn_readfirstlane(w1);
         v = __builtin_amdgcn_readfirstlane(v);
         int v_lo = P.ray_start[v], v_hi = P.ray_start[v + 1];

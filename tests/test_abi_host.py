@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), name
     assert set(_lib.SIGNATURES) == declared
-    assert api.abi_version() == 12
+    assert api.abi_version() == 13
 
 
 @pytest.mark.parametrize("n,depth,tau,seed", [(16, 4, 2.0, 1), (32, 5, 4.0, 2), (64, 4, 0.5, 3), (32, 0, 1.0, 4)])
@@ -254,7 +254,7 @@ def test_invalid_arguments_rejected_before_launch():
     dem = np.zeros(9, np.float32)
     _raise_einval("hfr_build_quadtree", dem.ctypes.data_as(ctypes.c_void_p), 3, 1.0, 0.0, 0.0, 1, 0.1,
                   ctypes.byref(q))
-    assert lib.hfr_abi_version() == 12
+    assert lib.hfr_abi_version() == 13
 
 
 def test_batch_arguments_rejected_before_any_device_call():
@@ -300,7 +300,7 @@ def test_batch_arguments_rejected_before_any_device_call():
                                                        dummy, 4, 3.5, 0.0, 0.0, 100.0, 7), dom
     _raise_einval("hfr_batch_plan_create", bad_basis, 1, view(), 1, ctypes.byref(h))
     assert h.value is None
-    t = _lib.BatchTuning(4, 4, 12, 4, 0)
+    t = _lib.BatchTuning(4, 4, 12, 4, 0, 8)
     _raise_einval("hfr_batch_set_tuning", None, ctypes.byref(t))
     _raise_einval("hfr_batch_long_rays", None, None)
     _raise_einval("hfr_batch_launch", None, None)

@@ -253,7 +253,9 @@ def test_backward_matches_oracle(gpu, batch):
                                     dict(disc_blocks_per_cu=8, ray_blocks_per_cu=2, ray_tile_w=16, disc_grain=64),
                                     dict(disc_blocks_per_cu=2, ray_blocks_per_cu=8, ray_tile_w=32, disc_grain=3),
                                     dict(disc_blocks_per_cu=4, ray_blocks_per_cu=4, ray_tile_w=8, disc_grain=8,
-                                         ray_queue=1)])
+                                         ray_queue=1),
+                                    dict(ray_tile_w=16, ray_grain=1),
+                                    dict(ray_blocks_per_cu=2, ray_queue=1, ray_grain=5)])
 def test_tuning_does_not_change_results(gpu, batch, tuning):
     R, cams, _ = batch
     R.set_tuning()
@@ -304,6 +306,9 @@ def test_tuning_rejects_a_bad_queue_switch(gpu, batch):
     R = batch[0]
     with pytest.raises(HfrError):
         R.set_tuning(ray_queue=2)
+    for grain in (0, 33):
+        with pytest.raises(HfrError):
+            R.set_tuning(ray_grain=grain)
     R.set_tuning()
 
 
