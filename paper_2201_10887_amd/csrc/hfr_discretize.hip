@@ -371,6 +371,13 @@ __device__ __forceinline__ void pair_weight_dsigma(float r2, float E, float* w, 
     }
 }
 
+// Value of x on lane t (t wave-uniform): a scalar read of one lane, no LDS
+// round trip.
+__device__ __forceinline__ float lane_value(float x, int t)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), t));
+}
+
 struct TileFrame {
     float x0, x1, y0, y1;  // tile rectangle relative to the block origin
     float npx, npy;        // minus the lane's texel centre relative to the block origin
@@ -650,19 +657,20 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
                     float acc_v = 0.0f, acc_s = 0.0f;
                     uint64_t m = active;
                     while (m) {
-                        const int t = __ffsll((unsigned long long)m) - 1;
+                        const int t = __ffsll((unsigned long long)m) - 1;  // wave-uniform
                         m &= m - 1;
-                        const float tnx = __shfl(f.npx, t), tny = __shfl(f.npy, t), tg = __shfl(gn, t),
-                                    tv = __shfl(vs, t);
+                        const float tnx = lane_value(f.npx, t), tny = lane_value(f.npy, t), tg = lane_value(gn, t),
+                                    tv = lane_value(vs, t);
                         const float dx = fmaf(tnx, q.z, q.x), dy = fmaf(tny, q.z, q.y);
                         const float r2 = fmaf(dx, dx, dy * dy);
                         float w, sdw;
                         pair_weight_dsigma<BASIS>(r2, E, &w, &sdw);
                         if (w > 0.0f) {
                             acc_v = fmaf(tg, w, acc_v);
-                            acc_s = fmaf(tg * (q.w - tv), sdw / sj, acc_s);
+                            acc_s = fmaf(tg * (q.w - tv), sdw, acc_s);
                         }
                     }
+                    acc_s /= sj;  // d w / d sigma = (sigma d w / d sigma) / sigma: one division per leaf
                     if (own && (acc_v != 0.0f || acc_s != 0.0f)) {
                         atomicAdd(&gv[bids[c]], acc_v);
                         atomicAdd(&gs[bids[c]], acc_s);
