@@ -173,6 +173,24 @@ def timed(fn, steps, stream):
     return a.elapsed_time(b) / steps
 
 
+def frame_times(fn, frames, warmup, stream):
+    """Each of ``frames`` calls timed on its own (HIP events on the stream, after ``warmup``
+    untimed calls): the median and the 10th / 90th percentiles in ms."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for f in range(frames):
+        fn()
+        ev[f + 1].record(stream)
+    torch.cuda.synchronize()
+    ts = np.sort([ev[f].elapsed_time(ev[f + 1]) for f in range(frames)])
+    return {"frames": frames, "median": round(float(np.median(ts)), 4), "p10": round(float(ts[frames // 10]), 4),
+            "p90": round(float(ts[(9 * frames) // 10]), 4)}
+
+
 def discretize_work(R, cas, leaves, w, samples=20000) -> dict:
     """Algorithmic work of one discretize pass (all K cascades), for the roofline.
 
@@ -511,6 +529,8 @@ def main():
     ms_fwd = timed(forward, args.steps, stream)
     ms_train = timed(train_step, args.steps, stream)
     print(f"[bench] forward {ms_fwd:.3f} ms, forward+backward {ms_train:.3f} ms", file=sys.stderr, flush=True)
+    # the frame time as a distribution: 100 frames after 10 warm-up frames, each timed on its own
+    per_frame = frame_times(forward, 100, 10, stream)
 
     # per-stage times on the same stream
     stage = {
@@ -611,6 +631,7 @@ def main():
         "data": "synthetic (seeded fBm terrain)",
         "config": {"workload": w.name, "leaves": int(R.L.n), "cascades": K, "tex_n": R.N,
                    "resolution": f"{W}x{H}", "sigma": w.sigma, "cutoff": w.cutoff, "split_lambda": w.split_lambda},
+        "frame_ms": per_frame,
         "fwd_bwd_ms": round(ms_train, 4),
         "fwd_bwd_over_fwd": round(ms_train / ms_fwd, 3),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
