@@ -567,7 +567,14 @@ def main():
             one = (api.Cascade * 1)(cas[k])
             stage[f"discretize_cascade{k}"] = (lambda one=one, k=k: api.discretize(R.L, R.dom, one, R.tex[k:k + 1],
                                                                                    R.mask[k:k + 1]))
-    stage_ms = {k: timed(f, args.steps, stream) for k, f in stage.items()}
+    def stage_time(f):
+        # two warm-up calls (the clocks settle after the host-side set-up above), then the median of
+        # three timing loops of `steps` calls each
+        f()
+        f()
+        return float(np.median([timed(f, args.steps, stream) for _ in range(3)]))
+
+    stage_ms = {k: stage_time(f) for k, f in stage.items()}
     del Lw, tex_w
     api.discretize(R.L, R.dom, cas, R.tex, R.mask)
     torch.cuda.synchronize()
