@@ -7,7 +7,9 @@ header of ``oracle/c/raycast_oracle.c``.  This module builds the rays
 Pinned by ``tests/test_oracle_raycast.py``: a tilted plane (bilinear
 interpolation is exact, so the depth has a closed form), a constant field,
 testing every cell of the texture by brute force, dense marching with
-bisection, and the blend invariants at the overlap ends.
+bisection, and the overlap blend against closed forms on cascades of
+different constant heights (both sweep directions, at the overlap's ends and
+at weights strictly inside).
 """
 from __future__ import annotations
 

@@ -194,7 +194,8 @@ def test_dense_marching_random_scene():
 
 @pytest.mark.parametrize("reverse", [False, True])
 def test_blend_rule_constant_cascades(reverse):
-    """Two cascades with different constant heights: depth follows the convex blend in the overlap."""
+    """Two cascades with different constant heights: depth follows the convex blend in the overlap,
+    at its ends and at weights strictly between them (closed-form hits and weights per ray)."""
     N, side = 64, 1000.0
     h = side / (N - 1)
     C1, C2 = 50.0, 45.0
@@ -213,7 +214,7 @@ def test_blend_rule_constant_cascades(reverse):
     d0 = (o[0] - origin[0]) * c1.vhat[0] + (o[1] - origin[1]) * c1.vhat[1]
     tA1, tB2 = (o[2] - C1) / -d[:, 2], (o[2] - C2) / -d[:, 2]
     dA1, dB2 = d0 + tA1 * dd, d0 + tB2 * dd
-    n_blend = 0
+    n_blend = n_inner = 0
     for a in range(len(d)):
         if d[a, 2] >= 0:
             assert not np.isfinite(r["depth"][a])
@@ -227,6 +228,7 @@ def test_blend_rule_constant_cascades(reverse):
                     al = (dA1[a] - s) / (far1 - s)
                     want = (1 - al) * tA1[a] + al * tB2[a]
                     n_blend += 1
+                    n_inner += 0.05 < al < 0.95
                 else:
                     want = tA1[a]
             else:
@@ -243,6 +245,7 @@ def test_blend_rule_constant_cascades(reverse):
                     al = (dB2[a] - s) / (far1 - s)
                     want = (1 - al) * tB + al * tB2[a]
                     n_blend += 1
+                    n_inner += 0.05 < al < 0.95
                 else:
                     want = tB2[a]
             else:
@@ -251,7 +254,7 @@ def test_blend_rule_constant_cascades(reverse):
             assert abs(r["depth"][a] - want) < 1e-9 * dom.extent, (a, r["depth"][a], want)
         else:
             assert not np.isfinite(r["depth"][a])
-    assert n_blend > 0
+    assert n_blend > 0 and n_inner > 0, (n_blend, n_inner)
 
 
 def test_ray_starting_below_surface_hits_at_entry():
