@@ -481,8 +481,9 @@ hfr_status hfr_discretize_backward(const hfr_leaves* L, const hfr_domain* dom,
  * every view), max-mipmap (one launch per five-level pass), ray casting
  * (one persistent launch for every pixel of every view), and for the
  * backward pass the two adjoints (one persistent launch each).  Persistent
- * workgroups take work from per-XCD queues and steal from other queues when
- * theirs is empty, so views of uneven size share the GPU without a launch
+ * workgroups (ray-cast waves) take runs of work from 64 chunk queues, eight
+ * per XCD, starting with one of their own XCD's and moving on to the others
+ * when it is empty, so views of uneven size share the GPU without a launch
  * per view.  The per-view work is the same as hfr_discretize,
  * hfr_build_maxmip and hfr_raycast (bit-identical outputs, with or without
  * the long-ray queue) and their adjoints; the batch is not in the paper,

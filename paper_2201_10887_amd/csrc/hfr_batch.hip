@@ -5,7 +5,7 @@
 // batch kernels call the same block and pixel bodies); what the plan adds is
 // the work distribution:
 //  - discretize and its adjoint: one persistent launch over all 16 x 16
-//    texel blocks of all cascades of all views (per-XCD queues);
+//    texel blocks of all cascades of all views (64 chunk queues, eight per XCD);
 //  - max-mipmap: one launch over the 64 x 64-cell tiles of all cascades, one for their top levels;
 //  - ray casting and its adjoint: one persistent launch over all 64-pixel
 //    tiles of all views, taken wave by wave; optionally (tuning.ray_queue)
