@@ -173,6 +173,26 @@ def timed(fn, steps, stream):
     return a.elapsed_time(b) / steps
 
 
+def copy_bandwidth_gbs(stream, nbytes=1 << 30, reps=5):
+    """HBM bandwidth a plain device-to-device copy reaches (bytes read + written per second), over
+    buffers four times the 256 MB last-level cache, median of ``reps`` copies after two untimed."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    del src, dst
+    return 2 * nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def frame_times(fn, frames, warmup, stream):
     """Each of ``frames`` calls timed on its own (HIP events on the stream, after ``warmup``
     untimed calls): the median and the 10th / 90th percentiles in ms."""
@@ -531,6 +551,7 @@ def main():
     print(f"[bench] forward {ms_fwd:.3f} ms, forward+backward {ms_train:.3f} ms", file=sys.stderr, flush=True)
     # the frame time as a distribution: 100 frames after 10 warm-up frames, each timed on its own
     per_frame = frame_times(forward, 100, 10, stream)
+    copy_gbs = copy_bandwidth_gbs(stream)
 
     # per-stage times on the same stream
     stage = {
@@ -661,9 +682,11 @@ def main():
         "maxmip_roofline": {"bound": "hbm", "achieved": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic_bytes": mip_bytes,
                             "frac": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "frac_of_copy": round(mip_bytes / (stage_ms["build_maxmip"] * 1e-3) / 1e9 / copy_gbs, 4),
                             "traffic": (recorded_traffic("paper_2201_10887_amd/csrc/hfr_maxmip.hip",
                                                          "profiles/maxmip_kernel_medium_hbm_counters.md")
                                         if args.workload == "medium" else None)},
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "dominant_stage": dominant,
         "roofline": roof,
     }
