@@ -542,8 +542,9 @@ typedef struct {
  * disc_grain: the most 16 x 16 texel blocks a discretize workgroup takes
  * per queue access, in [1, 64] (a share of what is left in its chunk of the
  * work, at most this many: small runs keep the blocks running at once close
- * together and the finish even, large runs need fewer atomics).  ray_queue: 1 = hfr_raycast's
- * long-ray queue for the batch (a ray still walking after 64 steps is queued
+ * together and the finish even, large runs need fewer atomics).
+ * ray_queue: 1 = hfr_raycast's long-ray queue for the batch (a ray still
+ * walking after 64 steps is queued
  * and finished by a second launch with 16 lanes per ray; the plan holds room
  * for a quarter of each view's pixels and a ray past that finishes in the
  * first launch), 0 = every ray finishes in the first launch; outputs are the
