@@ -619,11 +619,20 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
                     const float4 q0 = c < nb ? brec[c] : make_float4(0.f, 0.f, 0.f, 0.f);
                     const bool keep = c < nb && reaches(q0, f.x0, f.x1, f.y0, f.y1, lim);
                     uint64_t m = __ballot(keep);
+                    // two records per step (both reads in flight at once); a missing second
+                    // record is one that weighs exactly 0, so s0 sums the same terms in order
                     while (m) {
                         const int t = __ffsll((unsigned long long)m) - 1;
                         m &= m - 1;
-                        const float4 q = brec[c0 + t];
-                        s0 += pair_weight<BASIS>(fmaf(f.npx, q.z, q.x), fmaf(f.npy, q.z, q.y), E);
+                        const float4 qa = brec[c0 + t];
+                        float4 qb = make_float4(1e18f, 1e18f, 0.f, 0.f);
+                        if (m) {
+                            const int t2 = __ffsll((unsigned long long)m) - 1;
+                            m &= m - 1;
+                            qb = brec[c0 + t2];
+                        }
+                        s0 += pair_weight<BASIS>(fmaf(f.npx, qa.z, qa.x), fmaf(f.npy, qa.z, qa.y), E);
+                        s0 += pair_weight<BASIS>(fmaf(f.npx, qb.z, qb.x), fmaf(f.npy, qb.z, qb.y), E);
                     }
                 }
             }
@@ -659,9 +668,11 @@ __device__ __forceinline__ void discretize_backward_block(const Tables& T, const
                     while (m) {
                         const int t = __ffsll((unsigned long long)m) - 1;  // wave-uniform
                         m &= m - 1;
-                        const float tnx = lane_value(f.npx, t), tny = lane_value(f.npy, t), tg = lane_value(gn, t),
+                        // the texel offsets are read un-negated and negated in the multiply-add
+                        // (a lane read cannot take a negation modifier; the values are equal)
+                        const float tpx = lane_value(-f.npx, t), tpy = lane_value(-f.npy, t), tg = lane_value(gn, t),
                                     tv = lane_value(vs, t);
-                        const float dx = fmaf(tnx, q.z, q.x), dy = fmaf(tny, q.z, q.y);
+                        const float dx = fmaf(-tpx, q.z, q.x), dy = fmaf(-tpy, q.z, q.y);
                         const float r2 = fmaf(dx, dx, dy * dy);
                         float w, sdw;
                         pair_weight_dsigma<BASIS>(r2, E, &w, &sdw);
